@@ -1,0 +1,424 @@
+"""Pins of the FP64 oracle against values fixed by mathematics, not by the
+oracle itself: closed forms, invariants, LAPACK solves, an independent dense
+Kronecker implementation and brute force on tiny grids.
+
+Paper: arXiv:2110.13368, Eq. (1) (the model), section "Elements of
+Parallelism" (direction-by-direction line solves with axpy/naxpy, Dirichlet
+function), section "Methods of Validation" Method 1 (1-D convergence against
+an analytic solution with zero-flux ends).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2110_13368_amd import workloads as W
+from tests import dense_ref
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def make(shape, D, lam, dt=0.01, h=(20.0, 20.0, 20.0), mode=O.DECAY_ONCE, lo=None):
+    lo = W.centred_lo(shape, h) if lo is None else lo
+    return O.OracleSim(shape, h, lo, np.atleast_1d(D), np.atleast_1d(lam), dt, mode)
+
+
+# --------------------------------------------------------------------------
+# P3: every line solve equals LAPACK's dense solve of the same matrix.
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 17, 64, 203])
+@pytest.mark.parametrize("c", [0.0, 0.025, 2.5, 10.0])
+@pytest.mark.parametrize("sigma", [0.0, 1e-3 / 3])
+def test_thomas_matches_lapack(n, c, sigma):
+    rng = np.random.default_rng(n * 1000 + int(c * 10))
+    r = rng.uniform(-5, 40, size=n)
+    T = dense_ref.line_matrix(n, c, sigma)
+    x_ref = np.linalg.solve(T, r)
+    x = O.thomas_line(c, sigma, r)
+    assert rel(x, x_ref) < 1e-13
+    assert np.linalg.norm(T @ x - r) <= 1e-14 * np.linalg.norm(r) * (1 + 4 * c)
+
+
+def test_thomas_n1_is_division():
+    assert O.thomas_line(3.0, 0.5, [3.0])[0] == 2.0
+
+
+# --------------------------------------------------------------------------
+# P1: a uniform field with zero-flux faces only decays, exactly implicitly.
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_uniform_field_decay(mode):
+    shape = (7, 5, 4)
+    lam = np.array([0.1, 1.0, 0.0])
+    sim = make(shape, [1e5, 1e3, 5e4], lam, mode=mode)
+    rho0 = np.array([38.0, 1.5, 7.0])
+    sim.set_field(np.broadcast_to(rho0[:, None, None, None], sim.field_shape))
+    n = 25
+    sim.step(n)
+    got = sim.get_field()
+    if mode == O.DECAY_ONCE:
+        expect = rho0 * (1.0 + lam * 0.01) ** (-n)
+    else:
+        expect = rho0 * (1.0 + lam * 0.01 / 3.0) ** (-3 * n)
+    for s in range(3):
+        assert np.max(np.abs(got[s] - expect[s])) <= 1e-13 * expect[s]
+
+
+# --------------------------------------------------------------------------
+# P2: zero-flux faces conserve mass (lambda = 0), and with decay the mass is
+# multiplied by the exact per-step factor, for any field.
+
+def test_mass_conserved_neumann():
+    rng = np.random.default_rng(2)
+    sim = make((12, 10, 8), [1e5, 1e3], [0.0, 0.0], h=(10.0, 12.0, 9.0))
+    sim.set_field(rng.uniform(0, 40, size=sim.field_shape))
+    m0 = sim.mass()
+    sim.step(100)
+    assert np.max(np.abs(sim.mass() - m0) / m0) < 1e-12
+
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_mass_decays_by_exact_factor(mode):
+    rng = np.random.default_rng(3)
+    lam = np.array([0.3, 1e-3])
+    sim = make((9, 6, 11), [2e4, 7e4], lam, mode=mode)
+    sim.set_field(rng.uniform(0, 40, size=sim.field_shape))
+    m0 = sim.mass()
+    n = 40
+    sim.step(n)
+    f = 1.0 / (1.0 + lam * 0.01) if mode == O.DECAY_ONCE else (1.0 + lam * 0.01 / 3.0) ** -3
+    assert np.max(np.abs(sim.mass() - m0 * f ** n) / (m0 * f ** n)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P5: separable cosine modes are exact eigenvectors of every zero-flux line
+# matrix, so one step multiplies them by a known number.
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+@pytest.mark.parametrize("modes", [(1, 0, 0), (0, 2, 0), (0, 0, 3), (1, 2, 3), (4, 1, 2)])
+def test_cosine_mode_decay(mode, modes):
+    shape = (10, 7, 6)
+    h = (20.0, 15.0, 25.0)
+    D, lam, dt = 3e4, 0.2, 0.01
+    sim = make(shape, D, lam, dt=dt, h=h, mode=mode)
+    axes = [np.cos(k * np.pi * (np.arange(n) + 0.5) / n) for k, n in zip(modes, shape)]
+    u0 = np.einsum("k,j,i->kji", axes[2], axes[1], axes[0])
+    sim.set_field(u0[None])
+    sigma = lam * dt / 3.0 if mode == O.DECAY_THIRDS else 0.0
+    factor = 1.0 / (1.0 + lam * dt) if mode == O.DECAY_ONCE else 1.0
+    for k, n, hh in zip(modes, shape, h):
+        c = dt * D / hh ** 2
+        factor /= 1.0 + sigma + 4.0 * c * np.sin(k * np.pi / (2 * n)) ** 2
+    n_steps = 5
+    sim.step(n_steps)
+    assert np.max(np.abs(sim.get_field()[0] - factor ** n_steps * u0)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P6 (the paper's Method 1): 1-D diffusion with zero-flux ends from
+# u0 = A + B cos(pi x / L) against the analytic solution
+# A + B cos(pi x / L) exp(-D (pi/L)^2 t): first order in dt, second in dx.
+
+def _linf_1d(n, dt, t_end, D=1e3, L=1000.0, A=10.0, B=5.0):
+    h = L / n
+    sim = make((n, 1, 1), D, 0.0, dt=dt, h=(h, 7.0, 3.0), lo=(0.0, 0.0, 0.0))
+    x = (np.arange(n) + 0.5) * h
+    sim.set_field((A + B * np.cos(np.pi * x / L))[None, None, None, :])
+    steps = int(round(t_end / dt))
+    sim.step(steps)
+    exact = A + B * np.cos(np.pi * x / L) * np.exp(-D * (np.pi / L) ** 2 * steps * dt)
+    return np.max(np.abs(sim.get_field()[0, 0, 0] - exact))
+
+
+def test_convergence_1d_time():
+    errs = [_linf_1d(400, dt, 100.0) for dt in (4.0, 2.0, 1.0, 0.5)]
+    slope = np.polyfit(np.log([4.0, 2.0, 1.0, 0.5]), np.log(errs), 1)[0]
+    assert abs(slope - 1.0) < 0.15, (errs, slope)
+
+
+def test_convergence_1d_space():
+    ns = (8, 16, 32)
+    errs = [_linf_1d(n, 0.002, 100.0) for n in ns]
+    slope = np.polyfit(np.log([1.0 / n for n in ns]), np.log(errs), 1)[0]
+    assert abs(slope - 2.0) < 0.2, (errs, slope)
+
+
+# --------------------------------------------------------------------------
+# P7: with D = 0 and lambda = 0 the solves are the identity, and one cell drives
+# its voxel to rho_inf = S rho*/(S + U) geometrically with ratio 1/b.
+
+def test_single_cell_closed_form():
+    shape = (4, 3, 5)
+    h = (10.0, 10.0, 10.0)
+    sim = make(shape, 0.0, 0.0, h=h)
+    rho0 = 3.0
+    sim.set_field(np.full(sim.field_shape, rho0))
+    pos = np.array([[1.0, -2.0, 3.0]])
+    V, S, U, rs = 1500.0, 2.0, 0.5, 30.0
+    sim.upload_cells(pos, [V], [[S]], [[U]], [[rs]])
+    k = 0.01 * V / 1000.0
+    b = 1.0 + k * (S + U)
+    rho_inf = S * rs / (S + U)
+    n = 30
+    sim.step(n)
+    f = sim.get_field()[0].ravel()
+    v = dense_ref.cell_voxel(pos[0], shape, h, W.centred_lo(shape, h))
+    assert abs(f[v] - (rho_inf + (rho0 - rho_inf) * b ** (-n))) < 1e-14 * rho_inf
+    others = np.delete(f, v)
+    assert np.all(others == rho0)
+
+
+def test_two_cells_in_one_voxel_apply_in_index_order():
+    shape = (3, 3, 3)
+    sim = make(shape, 0.0, 0.0, h=(10.0, 10.0, 10.0))
+    sim.set_field(np.full(sim.field_shape, 5.0))
+    pos = np.array([[0.5, 0.5, 0.5], [1.5, 2.5, 0.1]])  # same centre voxel
+    V = np.array([1000.0, 3000.0])
+    S = np.array([[4.0], [0.0]])
+    U = np.array([[0.0], [7.0]])
+    rs = np.array([[20.0], [0.0]])
+    sim.upload_cells(pos, V, S, U, rs)
+    sim.sources()
+    k = 0.01 * V / 1000.0
+    a1, b1 = k[0] * 4.0 * 20.0, 1 + k[0] * 4.0
+    a2, b2 = 0.0, 1 + k[1] * 7.0
+    expect = (5.0 + a1 + a2 * b1) / (b1 * b2)
+    got = sim.get_field()[0, 1, 1, 1]
+    assert abs(got - expect) < 1e-14 * expect
+    swapped = (5.0 + a2 + a1 * b2) / (b1 * b2)
+    assert abs(got - swapped) > 1e-6  # the order is visible
+
+
+# --------------------------------------------------------------------------
+# P8 and Dirichlet precedence.
+
+def test_dirichlet_steady_state():
+    shape = (6, 5, 4)
+    sim = make(shape, 5e4, 0.0)
+    for f in range(6):
+        sim.set_boundary(0, f, O.DIRICHLET, 38.0)
+    sim.set_field(np.full(sim.field_shape, 38.0))
+    sim.step(50)
+    assert np.max(np.abs(sim.get_field() - 38.0)) < 1e-14 * 38.0
+
+
+def test_dirichlet_edges_take_last_active_face():
+    """With D = 0 and lambda = 0 the step reduces to the projection; every
+    boundary voxel must carry the value of the last active face among the faces
+    it lies on, in the order x-, x+, y-, y+, z-, z+."""
+    shape = (3, 4, 5)
+    sim = make(shape, 0.0, 0.0)
+    vals = [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    active = [True, True, False, True, True, False]
+    for f in range(6):
+        if active[f]:
+            sim.set_boundary(0, f, O.DIRICHLET, vals[f])
+    sim.set_field(np.full(sim.field_shape, -1.0))
+    sim.step(1)
+    got = sim.get_field()[0]
+    nx, ny, nz = shape
+    for k, j, i in itertools.product(range(nz), range(ny), range(nx)):
+        faces = [f for f, on in enumerate([i == 0, i == nx - 1, j == 0, j == ny - 1, k == 0, k == nz - 1])
+                 if on and active[f]]
+        expect = vals[max(faces)] if faces else -1.0
+        assert got[k, j, i] == expect, (i, j, k)
+
+
+# --------------------------------------------------------------------------
+# P4: a centred point source on an odd cube with zero-flux faces gives a field
+# invariant under all 48 symmetries of the cube (the directional solves
+# commute on a tensor grid, and each line matrix is persymmetric).
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_cube_symmetry(mode):
+    n = 21
+    sim = make((n, n, n), 4e4, 0.05, mode=mode)
+    sim.set_field(np.full(sim.field_shape, 2.0))
+    sim.upload_cells(np.zeros((1, 3)), [2494.0], [[10.0]], [[1.0]], [[40.0]])
+    sim.step(6)
+    f = sim.get_field()[0]
+    assert f[n // 2, n // 2, n // 2] > f[0, 0, 0]
+    scale = np.max(np.abs(f))
+    for perm in itertools.permutations(range(3)):
+        for flips in itertools.product([False, True], repeat=3):
+            g = np.transpose(f, perm)
+            for ax, fl in enumerate(flips):
+                if fl:
+                    g = np.flip(g, axis=ax)
+            assert np.max(np.abs(g - f)) <= 1e-13 * scale
+
+
+# --------------------------------------------------------------------------
+# P9: the whole step against the dense Kronecker implementation.
+
+TINY = [(5, 4, 3), (1, 1, 6), (6, 1, 1), (1, 5, 1), (2, 3, 4), (6, 6, 6), (1, 1, 1), (2, 2, 2)]
+
+
+@pytest.mark.parametrize("shape", TINY)
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+@pytest.mark.parametrize("bc", ["neumann", "dirichlet", "mixed"])
+def test_step_matches_dense_kronecker(shape, mode, bc):
+    rng = np.random.default_rng(hash((shape, mode, bc)) % 2**32)
+    spec = W.make_sim(rng, shape, (20.0, 13.0, 17.0), 2, dtype="f64", bc=bc, n_cells=9,
+                      cell_layout="uniform")
+    # force two cells into one voxel and one cell outside the grid
+    spec.cells.pos[1] = spec.cells.pos[0]
+    spec.cells.pos[2] = np.array(spec.lo) - 1.0
+    sim = O.from_spec(spec, decay_mode=mode)
+    ref = dense_ref.DenseLOD(spec.shape, spec.h, spec.lo, spec.D, spec.lam, spec.dt,
+                             spec.bc_kind, spec.bc_value, mode, spec.cells)
+    rho = spec.rho0.reshape(spec.n_sub, -1).astype(np.float64)
+    for _ in range(3):
+        rho = ref.step(rho)
+    sim.step(3)
+    got = sim.get_field().reshape(spec.n_sub, -1)
+    assert rel(got, rho) < 1e-12
+
+
+def test_cell_voxel_mapping_brute_force():
+    shape, h = (7, 5, 3), (10.0, 20.0, 30.0)
+    lo = (-35.0, -50.0, -45.0)
+    sim = O.OracleSim(shape, h, lo, [1.0], [0.0], 0.01)
+    # points on voxel faces, just inside, just outside and far away
+    rng = np.random.default_rng(7)
+    pts = [np.array(lo), np.array(lo) + np.array(shape) * np.array(h),
+           np.array(lo) + np.array(shape) * np.array(h) - 1e-9,
+           np.nextafter(np.array(lo), -np.inf), np.array([0.0, 0.0, 0.0]),
+           np.array([np.nan, 0.0, 0.0])]
+    pts += list(rng.uniform(np.array(lo) - 15, np.array(lo) + np.array(shape) * np.array(h) + 15,
+                            size=(300, 3)))
+    pos = np.array(pts)
+    n = len(pos)
+    n_out = sim.upload_cells(pos, np.ones(n), np.zeros((n, 1)), np.zeros((n, 1)), np.zeros((n, 1)))
+    got = sim.cell_voxels()
+    expect = []
+    for p in pos:
+        # brute force: the voxel whose half-open box contains p
+        hit = -1
+        for k, j, i in itertools.product(range(shape[2]), range(shape[1]), range(shape[0])):
+            c = (i, j, k)
+            if all(lo[a] + c[a] * h[a] <= p[a] < lo[a] + (c[a] + 1) * h[a] for a in range(3)):
+                hit = i + shape[0] * (j + shape[1] * k)
+        expect.append(hit)
+    # the brute force tests box membership on the lower/upper voxel faces; the
+    # oracle maps with floor((x - x0)/h).  They agree except where the division
+    # rounds across a face, which the chosen points avoid.
+    assert list(got) == expect
+    assert n_out == sum(1 for e in expect if e < 0)
+
+
+# --------------------------------------------------------------------------
+# P11: results do not depend on the thread count; stepping is resumable.
+
+def test_thread_count_and_resume_bitwise():
+    rng = np.random.default_rng(11)
+    spec = W.make_sim(rng, (17, 13, 9), (20.0, 20.0, 20.0), 3, dtype="f64", bc="mixed",
+                      n_cells=200, cell_layout="uniform")
+    outs = []
+    old = O.get_threads()
+    try:
+        for threads in (1, 4):
+            O.set_threads(threads)
+            sim = O.from_spec(spec)
+            sim.step(10)
+            outs.append(sim.get_field())
+    finally:
+        O.set_threads(old)
+    assert np.array_equal(outs[0], outs[1])
+    sim = O.from_spec(spec)
+    sim.step(4)
+    saved = sim.get_field()
+    sim2 = O.from_spec(spec)
+    sim2.set_field(saved)
+    sim2.step(6)
+    assert np.array_equal(sim2.get_field(), outs[0])
+
+
+# --------------------------------------------------------------------------
+# P10: the adjoint.  The step is affine in the field, so for the quadratic loss
+# L = 1/2 |rho_T - target|^2 a central difference along any direction is
+# exact up to rounding; parameters are checked with central differences.
+
+def _adjoint_case(mode, bc="mixed"):
+    rng = np.random.default_rng(101 + mode)
+    spec = W.make_sim(rng, (5, 4, 6), (20.0, 20.0, 20.0), 2, dtype="f64", bc=bc, n_cells=6,
+                      cell_layout="uniform")
+    spec.cells.pos[1] = spec.cells.pos[0]
+    target = rng.uniform(0, 40, size=spec.field_shape)
+    return spec, target
+
+
+def _loss(spec, target, mode, n_steps, rho0=None, D=None, lam=None, S=None, U=None):
+    import copy
+    sp = copy.deepcopy(spec)
+    if rho0 is not None:
+        sp.rho0 = rho0
+    if D is not None:
+        sp.D = D
+    if lam is not None:
+        sp.lam = lam
+    if S is not None:
+        sp.cells.S = S
+    if U is not None:
+        sp.cells.U = U
+    sim = O.from_spec(sp, decay_mode=mode)
+    sim.step(n_steps)
+    r = sim.get_field() - target
+    return 0.5 * np.sum(r * r), r
+
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_adjoint_field_dot_product(mode):
+    spec, target = _adjoint_case(mode)
+    n_steps = 7
+    L0, r = _loss(spec, target, mode, n_steps)
+    sim = O.from_spec(spec, decay_mode=mode)
+    g = sim.adjoint(n_steps, r)
+    rng = np.random.default_rng(5)
+    delta = rng.normal(size=spec.field_shape)
+    eps = 1e-3
+    Lp, _ = _loss(spec, target, mode, n_steps, rho0=spec.rho0 + eps * delta)
+    Lm, _ = _loss(spec, target, mode, n_steps, rho0=spec.rho0 - eps * delta)
+    fd = (Lp - Lm) / (2 * eps)
+    assert abs(fd - np.sum(g["rho0"] * delta)) <= 1e-9 * abs(fd)
+    # the current field is left as it was
+    assert np.array_equal(sim.get_field(), spec.rho0)
+
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_adjoint_parameters_vs_central_differences(mode):
+    spec, target = _adjoint_case(mode)
+    n_steps = 5
+    _, r = _loss(spec, target, mode, n_steps)
+    g = O.from_spec(spec, decay_mode=mode).adjoint(n_steps, r)
+
+    def fd(name, idx, base):
+        hstep = 1e-4 * abs(base[idx])  # loss ~1e4: smaller steps drown in rounding
+        p, m = base.copy(), base.copy()
+        p[idx] += hstep
+        m[idx] -= hstep
+        Lp, _ = _loss(spec, target, mode, n_steps, **{name: p})
+        Lm, _ = _loss(spec, target, mode, n_steps, **{name: m})
+        return (Lp - Lm) / (2 * hstep)
+
+    checks = []
+    for s in range(spec.n_sub):
+        checks.append((g["D"][s], fd("D", s, spec.D)))
+        checks.append((g["lambda"][s], fd("lam", s, spec.lam)))
+    for (i, s) in [(0, 0), (1, 1), (3, 0), (5, 1)]:
+        checks.append((g["S"][i, s], fd("S", (i, s), spec.cells.S)))
+        checks.append((g["U"][i, s], fd("U", (i, s), spec.cells.U)))
+    scale = max(abs(b) for _, b in checks)
+    for a, b in checks:
+        assert abs(a - b) <= 1e-6 * max(abs(b), 1e-3 * scale), (a, b)
+
+
+def test_adjoint_out_of_domain_cell_has_zero_gradient():
+    spec, target = _adjoint_case(O.DECAY_ONCE)
+    spec.cells.pos[4] = np.array(spec.lo) - 5.0
+    _, r = _loss(spec, target, O.DECAY_ONCE, 3)
+    g = O.from_spec(spec).adjoint(3, r)
+    assert np.all(g["S"][4] == 0.0) and np.all(g["U"][4] == 0.0)
