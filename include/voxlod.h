@@ -1,0 +1,172 @@
+/*
+ * voxlod.h -- C ABI of the MI355X (gfx950) library for the locally
+ * one-dimensional (LOD) diffusion-decay step with cell secretion/uptake.
+ *
+ * Method: Stack, Macklin, Searles, Chandrasekaran, "OpenACC Acceleration of an
+ * Agent-Based Biological Simulation Framework", arXiv:2110.13368.
+ *   Eq. (1)  d(rho)/dt = D lap(rho) - lambda rho
+ *                        + sum_i delta(x - x_i) V_i (S_i (rho*_i - rho) - U_i rho)
+ *   Section "Elements of Parallelism": the diffusion-decay part is solved
+ *   direction by direction (x, y, z), each direction as independent line
+ *   solves built from an elimination and a back-substitution over the
+ *   substrate vector, with Dirichlet conditions applied by their own function;
+ *   the field and the auxiliary arrays stay resident on the device.
+ *   Section "Future Work": cell secretion/uptake moved onto the device.
+ *
+ * One step, for every simulation and substrate s (c = dt*D_s/h_a^2):
+ *   rho <- C . P_D . S_z . P_D . S_y . P_D . F . S_x . P_D (rho)
+ *   S_a  solves tridiag(-c, b, -c) x = r on every line along axis a, with
+ *        zero-flux ends: b = 1 + c + sigma at both ends, 1 + 2c + sigma inside,
+ *        1 + sigma for a line of one voxel;
+ *   F    divides by (1 + lambda*dt) (VL_DECAY_ONCE, sigma = 0), or is the
+ *        identity with sigma = lambda*dt/3 in every S_a (VL_DECAY_THIRDS);
+ *   P_D  overwrites the outermost voxel layer of every Dirichlet face; on
+ *        edges and corners the last active face in the order x-, x+, y-, y+,
+ *        z-, z+ wins;
+ *   C    applies every cell, in the order it was uploaded, to the voxel that
+ *        holds it: rho <- (rho + k S rho*) / (1 + k (S + U)), k = dt V/V_vox.
+ *        A cell at x lies in voxel floor((x - x0)/dx) (per axis, half-open
+ *        grid); cells outside are skipped and counted.
+ *
+ * Memory.  The library never allocates device memory.  The caller allocates
+ * the field and a workspace of the sizes vl_finalize reports (normally as
+ * torch tensors) and passes raw device pointers to vl_bind; the caller keeps
+ * ownership and must keep both alive until vl_destroy.  Host arrays passed to
+ * any call are copied before the call returns.  Streams are borrowed
+ * (hipStream_t passed as void*).
+ *
+ * Field layout (device): per simulation, per substrate, a volume
+ * [z][y][x] with x fastest (structure of arrays), elements of the context's
+ * precision (float for VL_F32, double for VL_F64).  Every volume starts on a
+ * 256-byte boundary; vl_field_offset gives the element offset of a
+ * simulation's first volume and vl_volume_stride the distance between its
+ * substrates.
+ *
+ * Errors.  Every call returns VL_OK (0) or a negative VL_E_* code; the message
+ * of the last failure on the calling thread is returned by vl_last_error()
+ * (valid until the next call on that thread).  Kernel faults surface at the
+ * next synchronising call (vl_sync, vl_mass, vl_get_field, vl_check_finite).
+ * A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef VOXLOD_H
+#define VOXLOD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VL_ABI_VERSION 1
+
+/* status codes */
+#define VL_OK 0
+#define VL_E_ARG (-1)       /* an argument is out of range or inconsistent   */
+#define VL_E_STATE (-2)     /* call not allowed in the context's current state */
+#define VL_E_SHAPE (-3)     /* sizes do not fit the reserved layout          */
+#define VL_E_HIP (-4)       /* the HIP runtime reported an error             */
+#define VL_E_NONFINITE (-5) /* a non-finite value was found                  */
+
+/* precision of field storage and of the line solves */
+#define VL_F32 0 /* FP32 field; coefficients computed in FP64 on the device */
+#define VL_F64 1 /* FP64 field, plain one-line-per-thread kernels           */
+
+/* placement of the decay term */
+#define VL_DECAY_ONCE 0   /* F = 1/(1 + lambda dt) after the x solve (default) */
+#define VL_DECAY_THIRDS 1 /* sigma = lambda dt / 3 on every direction         */
+
+/* boundary kinds, faces 0..5 = x-, x+, y-, y+, z-, z+ */
+#define VL_NEUMANN 0
+#define VL_DIRICHLET 1
+
+/* host-side field layouts for vl_set_field / vl_get_field */
+#define VL_SOA 0 /* [s][z][y][x]  */
+#define VL_AOS 1 /* [z][y][x][s]  (the paper's voxel-major order) */
+
+/* kernel kinds reported by vl_kernel_stats */
+#define VL_K_SWEEP_X 0
+#define VL_K_SWEEP_Y 1
+#define VL_K_SWEEP_Z 2
+#define VL_K_SOURCES 3
+#define VL_K_DIRICHLET 4
+#define VL_K_DECAY 5
+#define VL_K_COUNT 6
+
+typedef struct vl_ctx vl_ctx;
+
+int vl_abi_version(void);
+const char *vl_last_error(void);
+
+/* Lifecycle.  n_sims >= 1 independent simulations share one context and are
+ * stepped together (each launch covers all of them). */
+int vl_create(vl_ctx **out, int n_sims, int precision, int decay_split);
+int vl_destroy(vl_ctx *ctx);
+
+/* Per-simulation setup (before vl_finalize).
+ * vl_set_grid: nx, ny, nz >= 1 voxels of edges dx, dy, dz > 0 (um), lower
+ *   corner (x0, y0, z0).  Each volume must hold fewer than 2^28 voxels;
+ *   the FP32 path takes lines of at most 513 voxels.
+ * vl_set_substrates: n_sub >= 1, D[s] >= 0 (um^2/min), lambda[s] >= 0 (1/min).
+ *   All faces start zero-flux.
+ * vl_set_boundary: kind VL_NEUMANN or VL_DIRICHLET with a finite value.
+ * vl_reserve_cells: capacity for vl_upload_cells (default 0, max 2^24). */
+int vl_set_grid(vl_ctx *ctx, int sim, int nx, int ny, int nz, double dx, double dy,
+                double dz, double x0, double y0, double z0);
+int vl_set_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D,
+                      const double *lambda);
+int vl_set_boundary(vl_ctx *ctx, int sim, int sub, int face, int kind, double value);
+int vl_reserve_cells(vl_ctx *ctx, int sim, int max_cells);
+
+/* Fix the layout for time step dt > 0 and report the sizes the caller must
+ * allocate: *field_elems elements of the context's precision and
+ * *workspace_bytes bytes (256-byte aligned device memory). */
+int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_bytes);
+
+/* Attach device memory and a stream.  Computes the line-solve coefficients
+ * on the device (FP64 arithmetic) and uploads the launch tables.  May be called
+ * again to move to other buffers or another stream.  stream may be NULL
+ * (the null stream; steps are then launched without a graph). */
+int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream);
+
+int vl_field_offset(vl_ctx *ctx, int sim, size_t *elem_offset);
+int vl_volume_stride(vl_ctx *ctx, int sim, size_t *elems);
+
+/* Copy one simulation's field in or out.  src/dst hold n_sub*nz*ny*nx elements
+ * of the context's precision, host or device memory, in layout VL_SOA or
+ * VL_AOS.  vl_get_field synchronises the stream. */
+int vl_set_field(vl_ctx *ctx, int sim, const void *src, int src_is_device, int layout);
+int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout);
+
+/* Upload n cells of one simulation (host arrays, row-major): pos n x 3 (um),
+ * V n (um^3, > 0), S, U n x n_sub (1/min, >= 0), rho_star n x n_sub.  The
+ * order is the order of application.  On the device: voxel of each cell
+ * (FP64), stable sort by voxel, per occupied voxel the composite of its cells
+ * (FP64 arithmetic).  *n_out_of_domain (may be NULL) receives the number of
+ * cells outside the grid.  Synchronises the stream.  n = 0 removes all cells. */
+int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V,
+                    const double *S, const double *U, const double *rho_star,
+                    int *n_out_of_domain);
+
+/* Advance every simulation by n_steps steps, asynchronously on the bound
+ * stream.  With a non-null stream the step is captured once into a hipGraph
+ * and replayed; the graph is rebuilt after any change of cells or binding. */
+int vl_step(vl_ctx *ctx, int n_steps);
+int vl_sync(vl_ctx *ctx);
+
+/* Diagnostics (synchronising).  vl_mass: out[s] = sum over voxels of rho (FP64
+ * accumulation, deterministic order).  vl_check_finite: *bad = number of
+ * non-finite field values (status VL_E_NONFINITE when > 0). */
+int vl_mass(vl_ctx *ctx, int sim, double *out);
+int vl_check_finite(vl_ctx *ctx, long long *bad);
+
+/* Per-kernel timing.  While enabled, vl_step launches without a graph and
+ * brackets every kernel with HIP events on the bound stream.
+ * vl_kernel_stats synchronises and reports, for one VL_K_* kind, the number
+ * of launches and their summed duration since profiling was enabled. */
+int vl_set_profiling(vl_ctx *ctx, int enable);
+int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,323 @@
+"""ctypes binding of libvoxlod.so.
+
+The ``vl_*`` functions mirror ``include/voxlod.h`` one to one and only marshal
+arguments; every step of the computation runs in the library's HIP kernels.
+``Context`` is a convenience owner: it allocates the field and the workspace
+as torch tensors on the GPU, creates a (default-priority) torch stream and
+binds them, because the library itself never allocates device memory.
+
+Loading fails loudly when the library has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvoxlod.so")
+
+VL_OK, VL_E_ARG, VL_E_STATE, VL_E_SHAPE, VL_E_HIP, VL_E_NONFINITE = 0, -1, -2, -3, -4, -5
+VL_F32, VL_F64 = 0, 1
+VL_DECAY_ONCE, VL_DECAY_THIRDS = 0, 1
+VL_NEUMANN, VL_DIRICHLET = 0, 1
+VL_SOA, VL_AOS = 0, 1
+VL_K_SWEEP_X, VL_K_SWEEP_Y, VL_K_SWEEP_Z, VL_K_SOURCES, VL_K_DIRICHLET, VL_K_DECAY = range(6)
+KERNEL_NAMES = ["sweep_x", "sweep_y", "sweep_z", "sources", "dirichlet", "decay"]
+
+# exported symbol -> (restype, argtypes)
+_vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+_dp, _ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+SIGNATURES = {
+    "vl_abi_version": (_i, []),
+    "vl_last_error": (C.c_char_p, []),
+    "vl_create": (_i, [C.POINTER(_vp), _i, _i, _i]),
+    "vl_destroy": (_i, [_vp]),
+    "vl_set_grid": (_i, [_vp, _i, _i, _i, _i, _d, _d, _d, _d, _d, _d]),
+    "vl_set_substrates": (_i, [_vp, _i, _i, _dp, _dp]),
+    "vl_set_boundary": (_i, [_vp, _i, _i, _i, _i, _d]),
+    "vl_reserve_cells": (_i, [_vp, _i, _i]),
+    "vl_finalize": (_i, [_vp, _d, C.POINTER(_sz), C.POINTER(_sz)]),
+    "vl_bind": (_i, [_vp, _vp, _vp, _vp]),
+    "vl_field_offset": (_i, [_vp, _i, C.POINTER(_sz)]),
+    "vl_volume_stride": (_i, [_vp, _i, C.POINTER(_sz)]),
+    "vl_set_field": (_i, [_vp, _i, _vp, _i, _i]),
+    "vl_get_field": (_i, [_vp, _i, _vp, _i, _i]),
+    "vl_upload_cells": (_i, [_vp, _i, _i, _dp, _dp, _dp, _dp, _dp, _ip]),
+    "vl_step": (_i, [_vp, _i]),
+    "vl_sync": (_i, [_vp]),
+    "vl_mass": (_i, [_vp, _i, _dp]),
+    "vl_check_finite": (_i, [_vp, C.POINTER(C.c_longlong)]),
+    "vl_set_profiling": (_i, [_vp, _i]),
+    "vl_kernel_stats": (_i, [_vp, _i, C.POINTER(C.c_longlong), _dp]),
+}
+
+_lib = None
+
+
+class VoxlodError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: status {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libvoxlod.so (raises if it is missing or unloadable)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2110_13368_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != VL_OK:
+        raise VoxlodError(rc, where, vl_last_error())
+    return rc
+
+
+def _f64(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+# ---------------------------------------------------------------------------
+# One wrapper per exported function (same names as the C ABI).
+
+def vl_abi_version() -> int:
+    return lib().vl_abi_version()
+
+
+def vl_last_error() -> str:
+    return lib().vl_last_error().decode(errors="replace")
+
+
+def vl_create(n_sims: int, precision: int = VL_F32, decay_split: int = VL_DECAY_ONCE):
+    h = _vp()
+    _check(lib().vl_create(C.byref(h), int(n_sims), int(precision), int(decay_split)), "vl_create")
+    return h
+
+
+def vl_destroy(ctx) -> None:
+    lib().vl_destroy(ctx)
+
+
+def vl_set_grid(ctx, sim, nx, ny, nz, dx, dy, dz, x0, y0, z0) -> None:
+    _check(lib().vl_set_grid(ctx, int(sim), int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                             float(x0), float(y0), float(z0)), "vl_set_grid")
+
+
+def vl_set_substrates(ctx, sim, D, lam) -> None:
+    D = _f64(D)
+    lam = _f64(lam, D.size)
+    _check(lib().vl_set_substrates(ctx, int(sim), D.size, _p(D), _p(lam)), "vl_set_substrates")
+
+
+def vl_set_boundary(ctx, sim, sub, face, kind, value) -> None:
+    _check(lib().vl_set_boundary(ctx, int(sim), int(sub), int(face), int(kind), float(value)),
+           "vl_set_boundary")
+
+
+def vl_reserve_cells(ctx, sim, max_cells) -> None:
+    _check(lib().vl_reserve_cells(ctx, int(sim), int(max_cells)), "vl_reserve_cells")
+
+
+def vl_finalize(ctx, dt):
+    fe, wb = _sz(0), _sz(0)
+    _check(lib().vl_finalize(ctx, float(dt), C.byref(fe), C.byref(wb)), "vl_finalize")
+    return int(fe.value), int(wb.value)
+
+
+def vl_bind(ctx, field_ptr: int, workspace_ptr: int, stream_ptr: int) -> None:
+    _check(lib().vl_bind(ctx, _vp(field_ptr), _vp(workspace_ptr), _vp(stream_ptr or None)), "vl_bind")
+
+
+def vl_field_offset(ctx, sim) -> int:
+    o = _sz(0)
+    _check(lib().vl_field_offset(ctx, int(sim), C.byref(o)), "vl_field_offset")
+    return int(o.value)
+
+
+def vl_volume_stride(ctx, sim) -> int:
+    o = _sz(0)
+    _check(lib().vl_volume_stride(ctx, int(sim), C.byref(o)), "vl_volume_stride")
+    return int(o.value)
+
+
+def vl_set_field(ctx, sim, src_ptr: int, src_is_device: bool, layout: int = VL_SOA) -> None:
+    _check(lib().vl_set_field(ctx, int(sim), _vp(src_ptr), int(bool(src_is_device)), int(layout)),
+           "vl_set_field")
+
+
+def vl_get_field(ctx, sim, dst_ptr: int, dst_is_device: bool, layout: int = VL_SOA) -> None:
+    _check(lib().vl_get_field(ctx, int(sim), _vp(dst_ptr), int(bool(dst_is_device)), int(layout)),
+           "vl_get_field")
+
+
+def vl_upload_cells(ctx, sim, pos, V, S, U, rho_star, n_sub: int) -> int:
+    pos = _f64(pos).reshape(-1, 3)
+    n = pos.shape[0]
+    V = _f64(V, n)
+    S = _f64(S, n * n_sub)
+    U = _f64(U, n * n_sub)
+    rs = _f64(rho_star, n * n_sub)
+    n_out = C.c_int(0)
+    _check(lib().vl_upload_cells(ctx, int(sim), n, _p(pos), _p(V), _p(S), _p(U), _p(rs), C.byref(n_out)),
+           "vl_upload_cells")
+    return int(n_out.value)
+
+
+def vl_step(ctx, n_steps: int) -> None:
+    _check(lib().vl_step(ctx, int(n_steps)), "vl_step")
+
+
+def vl_sync(ctx) -> None:
+    _check(lib().vl_sync(ctx), "vl_sync")
+
+
+def vl_mass(ctx, sim, n_sub: int) -> np.ndarray:
+    out = np.empty(n_sub, dtype=np.float64)
+    _check(lib().vl_mass(ctx, int(sim), _p(out)), "vl_mass")
+    return out
+
+
+def vl_check_finite(ctx) -> int:
+    bad = C.c_longlong(0)
+    rc = lib().vl_check_finite(ctx, C.byref(bad))
+    if rc not in (VL_OK, VL_E_NONFINITE):
+        _check(rc, "vl_check_finite")
+    return int(bad.value)
+
+
+def vl_set_profiling(ctx, enable: bool) -> None:
+    _check(lib().vl_set_profiling(ctx, int(bool(enable))), "vl_set_profiling")
+
+
+def vl_kernel_stats(ctx, kind: int):
+    n, ms = C.c_longlong(0), C.c_double(0)
+    _check(lib().vl_kernel_stats(ctx, int(kind), C.byref(n), C.byref(ms)), "vl_kernel_stats")
+    return int(n.value), float(ms.value)
+
+
+# ---------------------------------------------------------------------------
+
+class Context:
+    """Owns a library context for a list of simulations (workload ``SimSpec``
+    objects or anything with the same attributes), with its field and workspace
+    allocated as torch tensors on ``device`` and a torch stream of its own."""
+
+    def __init__(self, sims: Sequence, dt: Optional[float] = None, precision: int = VL_F32,
+                 decay_split: int = VL_DECAY_ONCE, device: str = "cuda:0", set_initial: bool = True,
+                 upload_cells: bool = True):
+        import torch
+        self.torch = torch
+        self.sims = list(sims)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == VL_F32 else torch.float64
+        self.np_dtype = np.float32 if precision == VL_F32 else np.float64
+        self.device = torch.device(device)
+        self.dt = float(dt if dt is not None else self.sims[0].dt)
+        self.h = vl_create(len(self.sims), precision, decay_split)
+        try:
+            for k, s in enumerate(self.sims):
+                vl_set_grid(self.h, k, *s.shape, *s.h, *s.lo)
+                vl_set_substrates(self.h, k, s.D, s.lam)
+                for q in range(s.n_sub):
+                    for f in range(6):
+                        if int(s.bc_kind[q, f]) == VL_DIRICHLET:
+                            vl_set_boundary(self.h, k, q, f, VL_DIRICHLET, float(s.bc_value[q, f]))
+                ncell = s.cells.n if getattr(s, "cells", None) is not None else 0
+                vl_reserve_cells(self.h, k, ncell)
+            self.field_elems, self.ws_bytes = vl_finalize(self.h, self.dt)
+            with torch.cuda.device(self.device):
+                self.stream = torch.cuda.Stream(device=self.device)
+            self.field = torch.zeros(self.field_elems, dtype=self.dtype, device=self.device)
+            self.workspace = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+            vl_bind(self.h, self.field.data_ptr(), self.workspace.data_ptr(), self.stream.cuda_stream)
+            self.offsets = [vl_field_offset(self.h, k) for k in range(len(self.sims))]
+            self.strides = [vl_volume_stride(self.h, k) for k in range(len(self.sims))]
+            if set_initial:
+                for k, s in enumerate(self.sims):
+                    self.set_field(k, s.rho0)
+            if upload_cells:
+                self.n_out = [self.upload_cells(k, s.cells) if s.cells.n > 0 else 0
+                              for k, s in enumerate(self.sims)]
+        except Exception:
+            vl_destroy(self.h)
+            self.h = None
+            raise
+
+    def close(self):
+        if getattr(self, "h", None):
+            vl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- field I/O --
+    def set_field(self, k: int, rho) -> None:
+        s = self.sims[k]
+        if isinstance(rho, self.torch.Tensor):
+            t = rho.to(self.device, self.dtype).contiguous()
+            self.torch.cuda.synchronize(self.device)
+            vl_set_field(self.h, k, t.data_ptr(), True, VL_SOA)
+        else:
+            a = np.ascontiguousarray(np.asarray(rho, dtype=self.np_dtype).reshape(s.field_shape))
+            vl_set_field(self.h, k, a.ctypes.data, False, VL_SOA)
+
+    def get_field(self, k: int) -> np.ndarray:
+        s = self.sims[k]
+        out = np.empty(s.field_shape, dtype=self.np_dtype)
+        vl_get_field(self.h, k, out.ctypes.data, False, VL_SOA)
+        return out
+
+    def field_view(self, k: int):
+        """Torch view (n_sub, nz, ny, nx) of one simulation's volumes."""
+        s = self.sims[k]
+        nx, ny, nz = s.shape
+        return self.field.as_strided((s.n_sub, nz, ny, nx), (self.strides[k], nx * ny, nx, 1),
+                                     self.offsets[k])
+
+    def upload_cells(self, k: int, cells) -> int:
+        return vl_upload_cells(self.h, k, cells.pos, cells.V, cells.S, cells.U, cells.rho_star,
+                               self.sims[k].n_sub)
+
+    # -- stepping and diagnostics --
+    def step(self, n: int = 1) -> None:
+        vl_step(self.h, n)
+
+    def sync(self) -> None:
+        vl_sync(self.h)
+
+    def mass(self, k: int) -> np.ndarray:
+        return vl_mass(self.h, k, self.sims[k].n_sub)
+
+    def check_finite(self) -> int:
+        return vl_check_finite(self.h)
+
+    def set_profiling(self, on: bool) -> None:
+        vl_set_profiling(self.h, on)
+
+    def kernel_stats(self):
+        return {KERNEL_NAMES[k]: vl_kernel_stats(self.h, k) for k in range(len(KERNEL_NAMES))}

@@ -1,0 +1,120 @@
+// vl_internal.h -- device-visible descriptors shared by the host runtime and
+// the gfx950 kernels of the LOD diffusion-decay library.  Internal: not part of
+// the C ABI (include/voxlod.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vl {
+
+// Lines per tile of the FP32 sweeps.  A tile is solved by one workgroup of two
+// waves: wave 0 eliminates the first half of each line top-down, wave 1 the
+// second half bottom-up; lane l of both waves owns line l of the tile.
+constexpr int kTileLines = 64;
+constexpr int kWave = 64;
+
+// Per-lane capacities (elements of one half line held in VGPRs) compiled for
+// the FP32 sweeps.  A sweep class uses the smallest one >= ceil((n-1)/2).
+constexpr int kNumCaps = 7;
+constexpr int kCaps[kNumCaps] = {32, 64, 96, 128, 160, 200, 256};
+
+// One (simulation, substrate) volume.
+struct SubDev {
+    long long base;      // element offset of voxel (0,0,0) in the field
+    long long vol;       // voxels in the volume (nx*ny*nz)
+    int n[3];            // nx, ny, nz
+    int sim;             // owning simulation
+    int sub;             // substrate index within the simulation
+    int dir_mask;        // bit f set: face f (x-, x+, y-, y+, z-, z+) is Dirichlet
+    int coef32[3];       // per axis: first float2 of the half-line table
+    int coef64[3];       // per axis: first double2 of the full-line table
+    float dval32[6];     // Dirichlet values (FP32 path)
+    float mid32[3][2];   // per axis: (g1, g2) of the middle row of the split solve
+    double dval64[6];    // Dirichlet values (FP64 path)
+    double c[3];         // dt*D/h_a^2 per axis
+    double sigma;        // diagonal shift lambda*dt/3 (decay split over the solves) or 0
+    double fdec;         // decay factor 1/(1 + lambda*dt) applied after the x solve, or 1
+    int pad_[2];
+};
+
+// One launch of an FP32 sweep over a group of volumes sharing a capacity
+// class: tiles of the listed volumes are numbered consecutively.
+struct SweepLaunch {
+    const int *sub_ids;      // volumes in this launch
+    const int *tile_prefix;  // count+1 exclusive prefix of their tile counts
+    int count;
+    int total_tiles;
+};
+
+// Per-simulation cell tables (all offsets in elements of their arrays).
+struct SimCells {
+    int sub0;        // index of the simulation's first SubDev (substrate 0)
+    int ns;          // substrates
+    int n_occ;       // occupied voxels
+    int occ_base;    // first entry in occ_vox / seg_start
+    int cell_base;   // first entry of the sorted per-cell arrays
+    int comp_base;   // first float2 of the FP32 composites (n_occ x ns)
+    int ab_base;     // first double2 of the sorted per-cell (a, b) (n_cells x ns)
+    int pad_;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files, called by the runtime).
+
+// a1: coefficients.  One thread per (volume, axis), FP64 recurrences.
+hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
+                               double2 *coef64, SubDev *subs_rw, hipStream_t st);
+
+// a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
+hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
+                            const SubDev *subs, const float2 *coef, float *field,
+                            hipStream_t st);
+
+// FP64 plain path: one thread per line, Thomas with the intermediate kept in
+// the field itself.  lines_prefix has nsubs+1 entries.
+hipError_t launch_sweep_plain(int axis, const SubDev *subs, int nsubs,
+                              const long long *lines_prefix, long long total_lines,
+                              const double2 *coef, double *field, hipStream_t st);
+hipError_t launch_dirichlet_plain(const SubDev *subs, const int4 *faces, int nfaces,
+                                  const long long *face_prefix, long long total,
+                                  double *field, hipStream_t st);
+hipError_t launch_decay_plain(const SubDev *subs, int nsubs, const long long *vox_prefix,
+                              long long total, double *field, hipStream_t st);
+
+// a2: cell binning.
+hipError_t launch_cell_keys(const double *pos, int n, int nx, int ny, int nz, double x0,
+                            double y0, double z0, double dx, double dy, double dz,
+                            unsigned long long *keys, int n_pad, int *n_out,
+                            hipStream_t st);
+hipError_t launch_bitonic_sort(unsigned long long *keys, int n_pad, hipStream_t st);
+hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id,
+                           int *occ_vox, int *seg_start, int *n_occ, hipStream_t st);
+hipError_t launch_composites(const unsigned long long *keys, const int *seg_start,
+                             int n_occ, int ns, const double *V, const double *S,
+                             const double *U, const double *RS, double dt, double vvox,
+                             float2 *comp32, double2 *ab64, int n_in, hipStream_t st);
+
+// a5/a6: sources over the occupied voxels of every simulation.
+hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix,
+                              int total_occ, int max_ns, const SubDev *subs,
+                              const int *occ_vox, const float2 *comp, float *field,
+                              hipStream_t st);
+hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ_prefix,
+                                int total_occ, const SubDev *subs, const int *occ_vox,
+                                const int *seg_start, const double2 *ab, double *field,
+                                hipStream_t st);
+
+// a7: FP64 mass of one volume; partials has kMassBlocks entries.
+constexpr int kMassBlocks = 256;
+hipError_t launch_mass(const void *field, int is_f64, long long base, long long vol,
+                       double *partials, double *out, hipStream_t st);
+hipError_t launch_count_nonfinite(const void *field, int is_f64, const SubDev *subs,
+                                  int nsubs, unsigned long long *count, hipStream_t st);
+
+// AoS <-> SoA on the device for one simulation.
+hipError_t launch_aos_to_soa(const void *src, void *field, int is_f64, long long base,
+                             long long vol_stride, long long vol, int ns, int inverse,
+                             hipStream_t st);
+
+}  // namespace vl

@@ -1,0 +1,608 @@
+// vl_kernels.hip -- coefficient precompute, the plain FP64 path, cell binning,
+// cell sources and diagnostics for gfx950.
+//
+// arXiv:2110.13368: Eq. (1) defines the model; section "Elements of
+// Parallelism" keeps the field and the auxiliary arrays resident on the
+// device, solves direction by direction with elimination/back-substitution and
+// applies Dirichlet conditions in a function of their own; section "Future
+// Work" names cell secretion/uptake as the next part to move onto the device.
+#include "vl_internal.h"
+
+namespace vl {
+
+// ---------------------------------------------------------------------------
+// a1: line-solve coefficients, FP64 recurrences, one thread per (volume, axis).
+//
+// Line matrix tridiag(-c, b, -c) with zero-flux ends: b_end = 1 + c + sigma,
+// b_in = 1 + 2c + sigma, and 1 + sigma for a one-voxel line.
+//  * full-line table (FP64 plain path): d_0 = b_0, d_i = b_i - c^2/d_{i-1};
+//    entries (1/d_i, c/d_i), i < n.
+//  * half-line table (FP32 split solve): pivots from one end, d_0 = b_end,
+//    d_t = b_in - c^2/d_{t-1}, t < cb = n - 1 - m with m = (n-1)/2; entries
+//    (f/d_t, c/d_t) where f is the decay factor folded into the x solve.
+//    Middle row m: gamma = b_m - c^2/d_{m-1} [m>0] - c^2/d_{cb-1} [cb>0],
+//    x_m = r_m f/gamma + (c/gamma) (y_{m-1} + z_{m+1}).
+__global__ void coefficients_kernel(SubDev *subs, int nsubs, float2 *coef32, double2 *coef64)
+{
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nsubs * 3) return;
+    SubDev &S = subs[id / 3];
+    const int a = id % 3;
+    const int n = S.n[a];
+    const double c = S.c[a];
+    const double sg = S.sigma;
+    const double f = (a == 0) ? S.fdec : 1.0;
+    const double b_in = 1.0 + 2.0 * c + sg;
+    const double b_end = (n == 1) ? 1.0 + sg : 1.0 + c + sg;
+
+    if (coef64) {
+        double2 *t64 = coef64 + S.coef64[a];
+        double d = b_end;
+        for (int i = 0; i < n; ++i) {
+            if (i > 0) d = ((i == n - 1) ? b_end : b_in) - c * c / d;
+            t64[i] = make_double2(1.0 / d, c / d);
+        }
+    }
+    if (coef32) {
+        float2 *t32 = coef32 + S.coef32[a];
+        const int m = (n - 1) / 2;
+        const int cb = n - 1 - m;
+        double d = b_end, d_m1 = 0.0, d_cb1 = 0.0;
+        for (int t = 0; t < cb; ++t) {
+            if (t > 0) d = b_in - c * c / d;
+            t32[t] = make_float2((float)(f / d), (float)(c / d));
+            if (t == m - 1) d_m1 = d;
+            if (t == cb - 1) d_cb1 = d;
+        }
+        const double b_m = (n == 1) ? 1.0 + sg : (n == 2 ? 1.0 + c + sg : b_in);
+        double gamma = b_m;
+        if (m > 0) gamma -= c * c / d_m1;
+        if (cb > 0) gamma -= c * c / d_cb1;
+        S.mid32[a][0] = (float)(f / gamma);
+        S.mid32[a][1] = (float)(c / gamma);
+    }
+}
+
+hipError_t launch_coefficients(const SubDev *, int nsubs, float2 *coef32, double2 *coef64,
+                               SubDev *subs_rw, hipStream_t st)
+{
+    const int threads = nsubs * 3;
+    if (threads == 0) return hipSuccess;
+    hipLaunchKernelGGL(coefficients_kernel, dim3((threads + 127) / 128), dim3(128), 0, st,
+                       subs_rw, nsubs, coef32, coef64);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain FP64 path: one thread per line, Thomas elimination writing y into the
+// field, back-substitution reading it back (the paper's per-direction loops).
+
+__device__ __forceinline__ int find_slot_ll(const long long *__restrict__ prefix, int count,
+                                            long long x)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int AXIS>
+__global__ void sweep_plain_kernel(const SubDev *__restrict__ subs, int nsubs,
+                                   const long long *__restrict__ lines_prefix,
+                                   long long total, const double2 *__restrict__ coef,
+                                   double *__restrict__ field)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int k = find_slot_ll(lines_prefix, nsubs, g);
+    const SubDev &S = subs[k];
+    const long long L = g - lines_prefix[k];
+    const long long nx = S.n[0], ny = S.n[1];
+    const int n = S.n[AXIS];
+    long long start, stride;
+    if (AXIS == 0) {
+        start = L * nx;
+        stride = 1;
+    } else if (AXIS == 1) {
+        start = (L % nx) + nx * ny * (L / nx);
+        stride = nx;
+    } else {
+        start = L;
+        stride = nx * ny;
+    }
+    double *p = field + S.base + start;
+    const double2 *cf = coef + S.coef64[AXIS];
+    const double c = S.c[AXIS];
+    double y = p[0] * cf[0].x;
+    p[0] = y;
+    for (int i = 1; i < n; ++i) {
+        y = (p[i * stride] + c * y) * cf[i].x;
+        p[i * stride] = y;
+    }
+    double x = y;
+    for (int i = n - 2; i >= 0; --i) {
+        x = p[i * stride] + cf[i].y * x;
+        p[i * stride] = x;
+    }
+}
+
+hipError_t launch_sweep_plain(int axis, const SubDev *subs, int nsubs,
+                              const long long *lines_prefix, long long total_lines,
+                              const double2 *coef, double *field, hipStream_t st)
+{
+    if (total_lines <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((total_lines + 255) / 256)), block(256);
+    if (axis == 0)
+        hipLaunchKernelGGL(sweep_plain_kernel<0>, grid, block, 0, st, subs, nsubs, lines_prefix, total_lines, coef, field);
+    else if (axis == 1)
+        hipLaunchKernelGGL(sweep_plain_kernel<1>, grid, block, 0, st, subs, nsubs, lines_prefix, total_lines, coef, field);
+    else
+        hipLaunchKernelGGL(sweep_plain_kernel<2>, grid, block, 0, st, subs, nsubs, lines_prefix, total_lines, coef, field);
+    return hipGetLastError();
+}
+
+// P_D over the Dirichlet faces.  faces[q] = (volume, face, 0, 0); one thread
+// per voxel of a face; every thread writes the value of the highest-numbered
+// active face containing its voxel, so voxels shared by faces get the same
+// value from every thread that touches them.
+__global__ void dirichlet_plain_kernel(const SubDev *__restrict__ subs, const int4 *__restrict__ faces,
+                                       int nfaces, const long long *__restrict__ face_prefix,
+                                       long long total, double *__restrict__ field)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int q = find_slot_ll(face_prefix, nfaces, g);
+    const int4 F = faces[q];
+    const SubDev &S = subs[F.x];
+    const int f = F.y;
+    const int a = f / 2;
+    const int au = (a == 0) ? 1 : 0, aw = (a == 2) ? 1 : 2;
+    const long long u_w = g - face_prefix[q];
+    int c[3];
+    c[a] = (f & 1) ? S.n[a] - 1 : 0;
+    c[au] = (int)(u_w % S.n[au]);
+    c[aw] = (int)(u_w / S.n[au]);
+    int best = -1;
+    for (int ff = 0; ff < 6; ++ff) {
+        const int aa = ff / 2;
+        const int layer = (ff & 1) ? S.n[aa] - 1 : 0;
+        if (((S.dir_mask >> ff) & 1) && c[aa] == layer) best = ff;
+    }
+    const long long v = c[0] + (long long)S.n[0] * (c[1] + (long long)S.n[1] * c[2]);
+    field[S.base + v] = S.dval64[best];
+}
+
+hipError_t launch_dirichlet_plain(const SubDev *subs, const int4 *faces, int nfaces,
+                                  const long long *face_prefix, long long total,
+                                  double *field, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dirichlet_plain_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       st, subs, faces, nfaces, face_prefix, total, field);
+    return hipGetLastError();
+}
+
+// F: rho <- rho / (1 + lambda dt), elementwise.
+__global__ void decay_plain_kernel(const SubDev *__restrict__ subs, int nsubs,
+                                   const long long *__restrict__ vox_prefix, long long total,
+                                   double *__restrict__ field)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int k = find_slot_ll(vox_prefix, nsubs, g);
+    const SubDev &S = subs[k];
+    double *p = field + S.base + (g - vox_prefix[k]);
+    *p = *p * S.fdec;
+}
+
+hipError_t launch_decay_plain(const SubDev *subs, int nsubs, const long long *vox_prefix,
+                              long long total, double *field, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(decay_plain_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       subs, nsubs, vox_prefix, total, field);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a2: cell binning.  Keys are (voxel << 24) | cell index, so sorting them
+// orders cells by voxel and, inside a voxel, by upload order; cells outside
+// the grid get the largest key and sort last.
+
+constexpr unsigned long long kNoVoxel = ~0ull;
+
+__global__ void cell_keys_kernel(const double *__restrict__ pos, int n, int nx, int ny, int nz,
+                                 double x0, double y0, double z0, double dx, double dy, double dz,
+                                 unsigned long long *__restrict__ keys, int n_pad, int *n_out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    if (i >= n) {
+        keys[i] = kNoVoxel;
+        return;
+    }
+    const double lo[3] = {x0, y0, z0}, h[3] = {dx, dy, dz};
+    const int nn[3] = {nx, ny, nz};
+    long long idx[3];
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) {
+        const double t = floor((pos[3 * (size_t)i + a] - lo[a]) / h[a]);
+        if (!(t >= 0.0) || !(t < (double)nn[a])) inside = false;
+        idx[a] = inside ? (long long)t : 0;
+    }
+    if (!inside) {
+        keys[i] = kNoVoxel;
+        atomicAdd(n_out, 1);
+        return;
+    }
+    const unsigned long long v = idx[0] + (long long)nx * (idx[1] + (long long)ny * idx[2]);
+    keys[i] = (v << 24) | (unsigned long long)i;
+}
+
+hipError_t launch_cell_keys(const double *pos, int n, int nx, int ny, int nz, double x0, double y0,
+                            double z0, double dx, double dy, double dz, unsigned long long *keys,
+                            int n_pad, int *n_out, hipStream_t st)
+{
+    if (n_pad <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cell_keys_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st, pos, n, nx, ny,
+                       nz, x0, y0, z0, dx, dy, dz, keys, n_pad, n_out);
+    return hipGetLastError();
+}
+
+// Bitonic sorting network (Batcher 1968) over n_pad = 2^p keys: for each
+// stage size k and distance j, element i is compared with i ^ j.  Keys are
+// unique, so the order is fully determined.
+__global__ void bitonic_global_kernel(unsigned long long *keys, int n_pad, int j, int k)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    const int l = i ^ j;
+    if (l <= i) return;
+    const unsigned long long a = keys[i], b = keys[l];
+    const bool up = (i & k) == 0;
+    if ((a > b) == up) {
+        keys[i] = b;
+        keys[l] = a;
+    }
+}
+
+// All distances j < 2048 of one stage k inside one block of 1024 threads
+// holding 2048 keys in LDS.
+__global__ void __launch_bounds__(1024) bitonic_local_kernel(unsigned long long *keys, int n_pad,
+                                                             int k_from, int k_to, int j_from)
+{
+    __shared__ unsigned long long s[2048];
+    const int base = blockIdx.x * 2048;
+    for (int t = threadIdx.x; t < 2048; t += 1024) s[t] = keys[base + t];
+    __syncthreads();
+    for (int k = k_from; k <= k_to; k <<= 1) {
+        for (int j = (k == k_from ? j_from : k >> 1); j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < 2048; t += 1024) {
+                const int l = t ^ j;
+                if (l > t) {
+                    const unsigned long long a = s[t], b = s[l];
+                    const bool up = ((base + t) & k) == 0;
+                    if ((a > b) == up) {
+                        s[t] = b;
+                        s[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < 2048; t += 1024) keys[base + t] = s[t];
+}
+
+hipError_t launch_bitonic_sort(unsigned long long *keys, int n_pad, hipStream_t st)
+{
+    if (n_pad <= 1) return hipSuccess;
+    if (n_pad < 2048) {
+        for (int k = 2; k <= n_pad; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1)
+                hipLaunchKernelGGL(bitonic_global_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st,
+                                   keys, n_pad, j, k);
+        return hipGetLastError();
+    }
+    const int nb = n_pad / 2048;
+    // stages k <= 2048 entirely in LDS
+    hipLaunchKernelGGL(bitonic_local_kernel, dim3(nb), dim3(1024), 0, st, keys, n_pad, 2, 2048, 1);
+    for (int k = 4096; k <= n_pad; k <<= 1) {
+        for (int j = k >> 1; j >= 2048; j >>= 1)
+            hipLaunchKernelGGL(bitonic_global_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st,
+                               keys, n_pad, j, k);
+        hipLaunchKernelGGL(bitonic_local_kernel, dim3(nb), dim3(1024), 0, st, keys, n_pad, k, k, 1024);
+    }
+    return hipGetLastError();
+}
+
+// Occupied voxels of the sorted keys (the first n_in are inside the grid):
+// a single workgroup scans the "new voxel" flags in order, so segment ids,
+// occupied-voxel list and segment starts come out in ascending voxel order.
+__global__ void __launch_bounds__(1024) segments_kernel(const unsigned long long *__restrict__ keys,
+                                                        int n_in, int *__restrict__ seg_id,
+                                                        int *__restrict__ occ_vox,
+                                                        int *__restrict__ seg_start, int *n_occ)
+{
+    __shared__ int warp_sums[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n_in; base += 1024) {
+        const int p = base + threadIdx.x;
+        int flag = 0;
+        if (p < n_in) flag = (p == 0) || ((keys[p] >> 24) != (keys[p - 1] >> 24));
+        // inclusive scan in the block: waves by shuffles, then wave sums
+        int x = flag;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) warp_sums[w] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int q = 0; q < 16; ++q) {
+                const int t = warp_sums[q];
+                warp_sums[q] = acc;
+                acc += t;
+            }
+        }
+        __syncthreads();
+        const int incl = carry + warp_sums[w] + x;
+        if (p < n_in) {
+            const int sid = incl - 1;
+            seg_id[p] = sid;
+            if (flag) {
+                occ_vox[sid] = (int)(keys[p] >> 24);
+                seg_start[sid] = p;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *n_occ = carry;
+        seg_start[carry] = n_in;
+    }
+}
+
+hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id, int *occ_vox,
+                           int *seg_start, int *n_occ, hipStream_t st)
+{
+    hipLaunchKernelGGL(segments_kernel, dim3(1), dim3(1024), 0, st, keys, n_in, seg_id, occ_vox,
+                       seg_start, n_occ);
+    return hipGetLastError();
+}
+
+// Per occupied voxel and substrate, walk its cells in upload order (FP64):
+//   a_i = k_i S_i rho*_i,  b_i = 1 + k_i (S_i + U_i),  k_i = dt V_i / V_vox,
+//   composite: A <- A + a_i B,  B <- B b_i  so that applying the cells one
+//   after another equals rho <- (rho + A) / B.
+// FP32 path: (A, 1/B); FP64 path: the per-cell (a_i, b_i) in sorted order.
+__global__ void composites_kernel(const unsigned long long *__restrict__ keys,
+                                  const int *__restrict__ seg_start, int n_occ, int ns,
+                                  const double *__restrict__ V, const double *__restrict__ S,
+                                  const double *__restrict__ U, const double *__restrict__ RS,
+                                  double dt, double vvox, float2 *__restrict__ comp32,
+                                  double2 *__restrict__ ab64)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)n_occ * ns) return;
+    const int seg = (int)(g / ns), s = (int)(g % ns);
+    double A = 0.0, B = 1.0;
+    for (int p = seg_start[seg]; p < seg_start[seg + 1]; ++p) {
+        const int i = (int)(keys[p] & 0xFFFFFFull);
+        const double k = dt * V[i] / vvox;
+        const size_t q = (size_t)i * ns + s;
+        const double a = k * S[q] * RS[q];
+        const double b = 1.0 + k * (S[q] + U[q]);
+        if (ab64) ab64[(size_t)p * ns + s] = make_double2(a, b);
+        A = A + a * B;
+        B = B * b;
+    }
+    if (comp32) comp32[(size_t)seg * ns + s] = make_float2((float)A, (float)(1.0 / B));
+}
+
+hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, int n_occ, int ns,
+                             const double *V, const double *S, const double *U, const double *RS,
+                             double dt, double vvox, float2 *comp32, double2 *ab64, int n_in,
+                             hipStream_t st)
+{
+    (void)n_in;
+    const long long total = (long long)n_occ * ns;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(composites_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys,
+                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, comp32, ab64);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sources (C), after the last Dirichlet projection of the step.
+
+__device__ __forceinline__ int find_slot_i(const int *__restrict__ prefix, int count, int x)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// FP32: one thread per (occupied voxel, substrate); rho <- (rho + A) * (1/B).
+__global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims,
+                                   const int *__restrict__ occ_prefix, int total_occ,
+                                   const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
+                                   const float2 *__restrict__ comp, float *__restrict__ field)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (j >= total_occ) return;
+    const int sim = find_slot_i(occ_prefix, nsims, j);
+    const SimCells &C = cells[sim];
+    if (s >= C.ns) return;
+    const int jl = j - occ_prefix[sim];
+    const int v = occ_vox[C.occ_base + jl];
+    const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
+    float *p = field + subs[C.sub0 + s].base + v;
+    *p = (*p + ab.x) * ab.y;
+}
+
+hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+                              int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
+                              float *field, hipStream_t st)
+{
+    if (total_occ <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_f32_kernel, dim3((total_occ + 255) / 256, max_ns), dim3(256), 0, st,
+                       cells, nsims, occ_prefix, total_occ, subs, occ_vox, comp, field);
+    return hipGetLastError();
+}
+
+// FP64 plain path: one thread per occupied voxel, cells applied one after
+// another in upload order: rho <- (rho + a_i) / b_i.
+__global__ void sources_plain_kernel(const SimCells *__restrict__ cells, int nsims,
+                                     const int *__restrict__ occ_prefix, int total_occ,
+                                     const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
+                                     const int *__restrict__ seg_start, const double2 *__restrict__ ab,
+                                     double *__restrict__ field)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total_occ) return;
+    const int sim = find_slot_i(occ_prefix, nsims, j);
+    const SimCells &C = cells[sim];
+    const int jl = j - occ_prefix[sim];
+    const int v = occ_vox[C.occ_base + jl];
+    const int p0 = seg_start[C.occ_base + jl], p1 = seg_start[C.occ_base + jl + 1];
+    for (int s = 0; s < C.ns; ++s) {
+        double *p = field + subs[C.sub0 + s].base + v;
+        double r = *p;
+        for (int q = p0; q < p1; ++q) {
+            const double2 e = ab[C.ab_base + (size_t)q * C.ns + s];
+            r = (r + e.x) / e.y;
+        }
+        *p = r;
+    }
+}
+
+hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+                                const SubDev *subs, const int *occ_vox, const int *seg_start,
+                                const double2 *ab, double *field, hipStream_t st)
+{
+    if (total_occ <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_plain_kernel, dim3((total_occ + 255) / 256), dim3(256), 0, st, cells,
+                       nsims, occ_prefix, total_occ, subs, occ_vox, seg_start, ab, field);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a7: mass.  Fixed grid of kMassBlocks blocks, each summing a fixed strided
+// set of voxels and reducing in a fixed tree; a second one-block pass adds
+// the partials in block order.  The result does not depend on timing.
+
+template <typename T>
+__global__ void __launch_bounds__(256) mass_partial_kernel(const T *__restrict__ field, long long base,
+                                                           long long vol, double *__restrict__ partials)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < vol; v += stride)
+        acc += (double)field[base + v];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void mass_final_kernel(const double *__restrict__ partials, int n, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += partials[i];
+    *out = acc;
+}
+
+hipError_t launch_mass(const void *field, int is_f64, long long base, long long vol,
+                       double *partials, double *out, hipStream_t st)
+{
+    if (is_f64)
+        hipLaunchKernelGGL(mass_partial_kernel<double>, dim3(kMassBlocks), dim3(256), 0, st,
+                           (const double *)field, base, vol, partials);
+    else
+        hipLaunchKernelGGL(mass_partial_kernel<float>, dim3(kMassBlocks), dim3(256), 0, st,
+                           (const float *)field, base, vol, partials);
+    hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, st, partials, kMassBlocks, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void nonfinite_kernel(const T *__restrict__ field, const SubDev *__restrict__ subs,
+                                 unsigned long long *count)
+{
+    const SubDev &S = subs[blockIdx.y];
+    unsigned long long bad = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < S.vol; v += stride) {
+        const double x = (double)field[S.base + v];
+        bad += !isfinite(x);
+    }
+    if (bad) atomicAdd(count, bad);
+}
+
+hipError_t launch_count_nonfinite(const void *field, int is_f64, const SubDev *subs, int nsubs,
+                                  unsigned long long *count, hipStream_t st)
+{
+    if (nsubs <= 0) return hipSuccess;
+    const dim3 grid(128, nsubs);
+    if (is_f64)
+        hipLaunchKernelGGL(nonfinite_kernel<double>, grid, dim3(256), 0, st, (const double *)field, subs, count);
+    else
+        hipLaunchKernelGGL(nonfinite_kernel<float>, grid, dim3(256), 0, st, (const float *)field, subs, count);
+    return hipGetLastError();
+}
+
+// AoS [v][s] <-> the SoA volumes of one simulation (inverse = 1: SoA -> AoS).
+template <typename T>
+__global__ void aos_soa_kernel(const T *__restrict__ src, T *__restrict__ field, long long base,
+                               long long vol_stride, long long vol, int ns, int inverse)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= vol * ns) return;
+    const long long v = g / ns;
+    const int s = (int)(g % ns);
+    if (!inverse)
+        field[base + s * vol_stride + v] = src[g];
+    else
+        const_cast<T *>(src)[g] = field[base + s * vol_stride + v];
+}
+
+hipError_t launch_aos_to_soa(const void *src, void *field, int is_f64, long long base,
+                             long long vol_stride, long long vol, int ns, int inverse, hipStream_t st)
+{
+    const long long total = vol * ns;
+    if (total <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (is_f64)
+        hipLaunchKernelGGL(aos_soa_kernel<double>, grid, block, 0, st, (const double *)src, (double *)field,
+                           base, vol_stride, vol, ns, inverse);
+    else
+        hipLaunchKernelGGL(aos_soa_kernel<float>, grid, block, 0, st, (const float *)src, (float *)field,
+                           base, vol_stride, vol, ns, inverse);
+    return hipGetLastError();
+}
+
+}  // namespace vl

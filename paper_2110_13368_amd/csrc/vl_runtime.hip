@@ -1,0 +1,880 @@
+// vl_runtime.hip -- host side of the C ABI declared in include/voxlod.h:
+// validation, layout of the borrowed field and workspace, launch tables,
+// cell upload, stepping (hipGraph replay), diagnostics and kernel timing.
+#include "voxlod.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vl_internal.h"
+
+using vl::SubDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define VL_HIP(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(VL_E_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int next_pow2(int n)
+{
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+struct SimHost {
+    int n[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0};
+    double lo[3] = {0, 0, 0};
+    bool grid_set = false;
+    int ns = 0;
+    std::vector<double> D, lam;
+    std::vector<int> bc_kind;    // ns*6
+    std::vector<double> bc_val;  // ns*6
+    int max_cells = 0;
+    // layout
+    size_t field_off = 0;
+    size_t vol_stride = 0;
+    int sub0 = 0;
+    // cell tables
+    int occ_base = 0, comp_base = 0, ab_base = 0;
+    int n_cells = 0, n_occ = 0, n_out = 0;
+    long long nvox() const { return (long long)n[0] * n[1] * n[2]; }
+};
+
+struct Launch {
+    int axis, cap_idx, count, total_tiles;
+    size_t ids_off, prefix_off;  // element offsets into the int table
+};
+
+struct Rec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct vl_ctx {
+    int n_sims = 0;
+    int precision = VL_F32;
+    int decay = VL_DECAY_ONCE;
+    std::vector<SimHost> sims;
+    bool finalized = false;
+    bool bound = false;
+    double dt = 0.0;
+    size_t esize = 4;
+    size_t field_elems = 0;
+    size_t ws_bytes = 0;
+
+    std::vector<SubDev> subs;
+    std::vector<Launch> launches;
+    std::vector<int> itable;
+    std::vector<long long> lltable;
+    size_t lines_off[3] = {0, 0, 0};
+    long long total_lines[3] = {0, 0, 0};
+    size_t vox_off = 0, face_off = 0;
+    long long total_vox = 0, total_face = 0;
+    std::vector<int4> faces;
+    int max_ns = 0;
+    int cap_total = 0;     // sum over sims of (max_cells + 1)
+    int comp_total = 0;    // sum over sims of max_cells * ns
+    int stage_cells = 0;   // max over sims of max_cells
+    int stage_ns = 0;      // max over sims of ns
+    int key_pad = 0;       // next_pow2(stage_cells)
+
+    // workspace layout (byte offsets)
+    size_t o_subs = 0, o_coef32 = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0;
+    size_t o_cells = 0, o_occ_prefix = 0, o_occ_vox = 0, o_seg_start = 0, o_comp = 0, o_ab = 0;
+    size_t o_pos = 0, o_V = 0, o_S = 0, o_U = 0, o_RS = 0, o_keys = 0, o_seg_id = 0;
+    size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
+    size_t n_coef32 = 0, n_coef64 = 0;
+
+    char *ws = nullptr;
+    void *field = nullptr;
+    hipStream_t stream = nullptr;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_valid = false;
+
+    bool profiling = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+    long long k_launches[VL_K_COUNT] = {0};
+    double k_ms[VL_K_COUNT] = {0};
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+int check_ctx(vl_ctx *ctx)
+{
+    if (!ctx) return fail(VL_E_ARG, "null context");
+    return VL_OK;
+}
+
+int check_sim(vl_ctx *ctx, int sim)
+{
+    if (!ctx) return fail(VL_E_ARG, "null context");
+    if (sim < 0 || sim >= ctx->n_sims) return fail(VL_E_ARG, "simulation index out of range");
+    return VL_OK;
+}
+
+void drop_graph(vl_ctx *ctx)
+{
+    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_valid = false;
+}
+
+int cap_index(int cb)
+{
+    for (int i = 0; i < vl::kNumCaps; ++i)
+        if (vl::kCaps[i] >= cb) return i;
+    return -1;
+}
+
+// ---- timing --------------------------------------------------------------
+
+hipEvent_t take_event(vl_ctx *ctx)
+{
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int collect_events(vl_ctx *ctx)
+{
+    if (ctx->recs.empty()) return VL_OK;
+    VL_HIP(hipStreamSynchronize(ctx->stream));
+    for (const Rec &r : ctx->recs) {
+        float ms = 0.f;
+        VL_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        ctx->k_launches[r.kind] += 1;
+        ctx->k_ms[r.kind] += ms;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return VL_OK;
+}
+
+// Runs one launch, bracketed by events while profiling.
+template <typename F>
+int timed(vl_ctx *ctx, int kind, F &&launch)
+{
+    Rec r{kind, nullptr, nullptr};
+    if (ctx->profiling) {
+        r.a = take_event(ctx);
+        r.b = take_event(ctx);
+        if (!r.a || !r.b) return fail(VL_E_HIP, "hipEventCreate failed");
+        VL_HIP(hipEventRecord(r.a, ctx->stream));
+    }
+    VL_HIP(launch());
+    if (ctx->profiling) {
+        VL_HIP(hipEventRecord(r.b, ctx->stream));
+        ctx->recs.push_back(r);
+    }
+    return VL_OK;
+}
+
+// ---- one step ------------------------------------------------------------
+
+int enqueue_step(vl_ctx *ctx)
+{
+    hipStream_t st = ctx->stream;
+    const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
+    const int nsubs = (int)ctx->subs.size();
+    int total_occ = 0;
+    for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+    int rc;
+    if (ctx->precision == VL_F32) {
+        float *field = (float *)ctx->field;
+        const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+        for (int axis = 0; axis < 3; ++axis)
+            for (const Launch &L : ctx->launches) {
+                if (L.axis != axis) continue;
+                vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
+                                  ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles};
+                rc = timed(ctx, VL_K_SWEEP_X + axis, [&] {
+                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, st);
+                });
+                if (rc) return rc;
+            }
+        if (total_occ > 0) {
+            rc = timed(ctx, VL_K_SOURCES, [&] {
+                return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
+                                              ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
+                                              subs, ctx->at<int>(ctx->o_occ_vox),
+                                              ctx->at<float2>(ctx->o_comp), field, st);
+            });
+            if (rc) return rc;
+        }
+        return VL_OK;
+    }
+    // plain FP64 path: P_D, S_x, F, P_D, S_y, P_D, S_z, P_D, C as separate kernels
+    double *field = (double *)ctx->field;
+    const double2 *coef = ctx->at<double2>(ctx->o_coef64);
+    const long long *ll = ctx->at<long long>(ctx->o_lltable);
+    auto dirichlet = [&]() -> int {
+        if (ctx->total_face == 0) return VL_OK;
+        return timed(ctx, VL_K_DIRICHLET, [&] {
+            return vl::launch_dirichlet_plain(subs, ctx->at<int4>(ctx->o_faces), (int)ctx->faces.size(),
+                                              ll + ctx->face_off, ctx->total_face, field, st);
+        });
+    };
+    auto sweep = [&](int axis) -> int {
+        return timed(ctx, VL_K_SWEEP_X + axis, [&] {
+            return vl::launch_sweep_plain(axis, subs, nsubs, ll + ctx->lines_off[axis],
+                                          ctx->total_lines[axis], coef, field, st);
+        });
+    };
+    if ((rc = dirichlet())) return rc;
+    if ((rc = sweep(0))) return rc;
+    if (ctx->decay == VL_DECAY_ONCE) {
+        rc = timed(ctx, VL_K_DECAY, [&] {
+            return vl::launch_decay_plain(subs, nsubs, ll + ctx->vox_off, ctx->total_vox, field, st);
+        });
+        if (rc) return rc;
+    }
+    if ((rc = dirichlet())) return rc;
+    if ((rc = sweep(1))) return rc;
+    if ((rc = dirichlet())) return rc;
+    if ((rc = sweep(2))) return rc;
+    if ((rc = dirichlet())) return rc;
+    if (total_occ > 0) {
+        rc = timed(ctx, VL_K_SOURCES, [&] {
+            return vl::launch_sources_plain(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
+                                            ctx->at<int>(ctx->o_occ_prefix), total_occ, subs,
+                                            ctx->at<int>(ctx->o_occ_vox), ctx->at<int>(ctx->o_seg_start),
+                                            ctx->at<double2>(ctx->o_ab), field, st);
+        });
+        if (rc) return rc;
+    }
+    return VL_OK;
+}
+
+int upload_cell_tables(vl_ctx *ctx)
+{
+    std::vector<vl::SimCells> cells(ctx->n_sims);
+    std::vector<int> prefix(ctx->n_sims + 1, 0);
+    for (int k = 0; k < ctx->n_sims; ++k) {
+        const SimHost &s = ctx->sims[k];
+        cells[k] = vl::SimCells{s.sub0, s.ns, s.n_occ, s.occ_base, 0, s.comp_base, s.ab_base, 0};
+        prefix[k + 1] = prefix[k] + s.n_occ;
+    }
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_cells, cells.data(), cells.size() * sizeof(vl::SimCells),
+                          hipMemcpyHostToDevice, ctx->stream));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_occ_prefix, prefix.data(), prefix.size() * sizeof(int),
+                          hipMemcpyHostToDevice, ctx->stream));
+    VL_HIP(hipStreamSynchronize(ctx->stream));
+    return VL_OK;
+}
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+int vl_abi_version(void) { return VL_ABI_VERSION; }
+
+const char *vl_last_error(void) { return g_err.c_str(); }
+
+int vl_create(vl_ctx **out, int n_sims, int precision, int decay_split)
+{
+    if (!out) return fail(VL_E_ARG, "out is null");
+    *out = nullptr;
+    if (n_sims < 1 || n_sims > (1 << 20)) return fail(VL_E_ARG, "n_sims must be in [1, 2^20]");
+    if (precision != VL_F32 && precision != VL_F64) return fail(VL_E_ARG, "precision must be VL_F32 or VL_F64");
+    if (decay_split != VL_DECAY_ONCE && decay_split != VL_DECAY_THIRDS)
+        return fail(VL_E_ARG, "decay_split must be VL_DECAY_ONCE or VL_DECAY_THIRDS");
+    vl_ctx *ctx = new (std::nothrow) vl_ctx();
+    if (!ctx) return fail(VL_E_ARG, "out of host memory");
+    ctx->n_sims = n_sims;
+    ctx->precision = precision;
+    ctx->decay = decay_split;
+    ctx->esize = precision == VL_F32 ? 4 : 8;
+    ctx->sims.resize(n_sims);
+    *out = ctx;
+    return VL_OK;
+}
+
+int vl_destroy(vl_ctx *ctx)
+{
+    if (!ctx) return VL_OK;
+    drop_graph(ctx);
+    for (const Rec &r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return VL_OK;
+}
+
+int vl_set_grid(vl_ctx *ctx, int sim, int nx, int ny, int nz, double dx, double dy, double dz,
+                double x0, double y0, double z0)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (ctx->finalized) return fail(VL_E_STATE, "grid cannot change after vl_finalize");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(VL_E_ARG, "grid sizes must be >= 1");
+    const long long nv = (long long)nx * ny * nz;
+    if (nv >= (1ll << 31) / 8) return fail(VL_E_SHAPE, "a volume must hold fewer than 2^28 voxels");
+    const double hv[3] = {dx, dy, dz}, lv[3] = {x0, y0, z0};
+    for (int a = 0; a < 3; ++a) {
+        if (!(hv[a] > 0) || !std::isfinite(hv[a])) return fail(VL_E_ARG, "voxel edges must be finite and > 0");
+        if (!std::isfinite(lv[a])) return fail(VL_E_ARG, "grid corner must be finite");
+    }
+    SimHost &s = ctx->sims[sim];
+    s.n[0] = nx; s.n[1] = ny; s.n[2] = nz;
+    for (int a = 0; a < 3; ++a) {
+        s.h[a] = hv[a];
+        s.lo[a] = lv[a];
+    }
+    s.grid_set = true;
+    return VL_OK;
+}
+
+int vl_set_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D, const double *lambda)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (ctx->finalized) return fail(VL_E_STATE, "substrates cannot change after vl_finalize");
+    if (n_sub < 1 || n_sub > 4096) return fail(VL_E_ARG, "n_sub must be in [1, 4096]");
+    if (!D || !lambda) return fail(VL_E_ARG, "D and lambda must not be null");
+    for (int s = 0; s < n_sub; ++s)
+        if (!(D[s] >= 0) || !(lambda[s] >= 0) || !std::isfinite(D[s]) || !std::isfinite(lambda[s]))
+            return fail(VL_E_ARG, "D and lambda must be finite and >= 0");
+    SimHost &h = ctx->sims[sim];
+    h.ns = n_sub;
+    h.D.assign(D, D + n_sub);
+    h.lam.assign(lambda, lambda + n_sub);
+    h.bc_kind.assign((size_t)n_sub * 6, VL_NEUMANN);
+    h.bc_val.assign((size_t)n_sub * 6, 0.0);
+    return VL_OK;
+}
+
+int vl_set_boundary(vl_ctx *ctx, int sim, int sub, int face, int kind, double value)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (ctx->finalized) return fail(VL_E_STATE, "boundaries cannot change after vl_finalize");
+    SimHost &h = ctx->sims[sim];
+    if (sub < 0 || sub >= h.ns) return fail(VL_E_ARG, "substrate index out of range (set substrates first)");
+    if (face < 0 || face > 5) return fail(VL_E_ARG, "face must be in 0..5");
+    if (kind != VL_NEUMANN && kind != VL_DIRICHLET) return fail(VL_E_ARG, "kind must be VL_NEUMANN or VL_DIRICHLET");
+    if (!std::isfinite(value)) return fail(VL_E_ARG, "boundary value must be finite");
+    h.bc_kind[(size_t)sub * 6 + face] = kind;
+    h.bc_val[(size_t)sub * 6 + face] = value;
+    return VL_OK;
+}
+
+int vl_reserve_cells(vl_ctx *ctx, int sim, int max_cells)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (ctx->finalized) return fail(VL_E_STATE, "cell capacity cannot change after vl_finalize");
+    if (max_cells < 0 || max_cells > (1 << 24)) return fail(VL_E_ARG, "max_cells must be in [0, 2^24]");
+    ctx->sims[sim].max_cells = max_cells;
+    return VL_OK;
+}
+
+int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_bytes)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (ctx->finalized) return fail(VL_E_STATE, "context already finalized");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(VL_E_ARG, "dt must be finite and > 0");
+    for (int k = 0; k < ctx->n_sims; ++k) {
+        const SimHost &s = ctx->sims[k];
+        if (!s.grid_set) return fail(VL_E_STATE, "simulation " + std::to_string(k) + " has no grid");
+        if (s.ns < 1) return fail(VL_E_STATE, "simulation " + std::to_string(k) + " has no substrates");
+    }
+    ctx->dt = dt;
+    const size_t align = 256 / ctx->esize;
+
+    // field layout and volume descriptors
+    ctx->subs.clear();
+    size_t off = 0;
+    size_t c32 = 0, c64 = 0;
+    ctx->max_ns = 0;
+    for (int k = 0; k < ctx->n_sims; ++k) {
+        SimHost &s = ctx->sims[k];
+        s.field_off = off;
+        s.vol_stride = round_up((size_t)s.nvox(), align);
+        s.sub0 = (int)ctx->subs.size();
+        ctx->max_ns = std::max(ctx->max_ns, s.ns);
+        for (int q = 0; q < s.ns; ++q) {
+            SubDev d;
+            std::memset(&d, 0, sizeof d);
+            d.base = (long long)(off + (size_t)q * s.vol_stride);
+            d.vol = s.nvox();
+            for (int a = 0; a < 3; ++a) {
+                d.n[a] = s.n[a];
+                d.c[a] = dt * s.D[q] / (s.h[a] * s.h[a]);
+                d.coef64[a] = (int)c64;
+                d.coef32[a] = (int)c32;
+                c64 += (size_t)s.n[a];
+                c32 += (size_t)(s.n[a] - 1 - (s.n[a] - 1) / 2);
+            }
+            d.sim = k;
+            d.sub = q;
+            d.sigma = ctx->decay == VL_DECAY_THIRDS ? s.lam[q] * dt / 3.0 : 0.0;
+            d.fdec = ctx->decay == VL_DECAY_ONCE ? 1.0 / (1.0 + s.lam[q] * dt) : 1.0;
+            for (int f = 0; f < 6; ++f) {
+                if (s.bc_kind[(size_t)q * 6 + f] == VL_DIRICHLET) d.dir_mask |= 1 << f;
+                d.dval64[f] = s.bc_val[(size_t)q * 6 + f];
+                d.dval32[f] = (float)s.bc_val[(size_t)q * 6 + f];
+            }
+            ctx->subs.push_back(d);
+        }
+        off += (size_t)s.ns * s.vol_stride;
+    }
+    if (c64 >= (1ull << 31) || c32 >= (1ull << 31)) return fail(VL_E_SHAPE, "too many coefficients");
+    ctx->field_elems = off;
+    ctx->n_coef32 = std::max<size_t>(c32, 1);
+    ctx->n_coef64 = std::max<size_t>(c64, 1);
+    const int nsubs = (int)ctx->subs.size();
+
+    // FP32 sweep launches: volumes grouped by the capacity class of each axis
+    ctx->launches.clear();
+    ctx->itable.clear();
+    if (ctx->precision == VL_F32) {
+        for (int axis = 0; axis < 3; ++axis) {
+            std::vector<std::vector<int>> groups(vl::kNumCaps);
+            for (int q = 0; q < nsubs; ++q) {
+                const int n = ctx->subs[q].n[axis];
+                const int ci = cap_index(n - 1 - (n - 1) / 2);
+                if (ci < 0)
+                    return fail(VL_E_SHAPE, "FP32 path: lines longer than " +
+                                                std::to_string(2 * vl::kCaps[vl::kNumCaps - 1] + 1) +
+                                                " voxels are not supported");
+                groups[ci].push_back(q);
+            }
+            for (int ci = 0; ci < vl::kNumCaps; ++ci) {
+                if (groups[ci].empty()) continue;
+                Launch L;
+                L.axis = axis;
+                L.cap_idx = ci;
+                L.count = (int)groups[ci].size();
+                L.ids_off = ctx->itable.size();
+                for (int q : groups[ci]) ctx->itable.push_back(q);
+                L.prefix_off = ctx->itable.size();
+                long long acc = 0;
+                for (int q : groups[ci]) {
+                    ctx->itable.push_back((int)acc);
+                    const SubDev &d = ctx->subs[q];
+                    const long long nxb = (d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
+                    long long tiles;
+                    if (axis == 0)
+                        tiles = ((long long)d.n[1] * d.n[2] + vl::kTileLines - 1) / vl::kTileLines;
+                    else if (axis == 1)
+                        tiles = nxb * d.n[2];
+                    else
+                        tiles = nxb * d.n[1];
+                    acc += tiles;
+                    if (acc >= (1ll << 31)) return fail(VL_E_SHAPE, "too many tiles in one launch");
+                }
+                ctx->itable.push_back((int)acc);
+                L.total_tiles = (int)acc;
+                ctx->launches.push_back(L);
+            }
+        }
+    }
+    if (ctx->itable.empty()) ctx->itable.push_back(0);
+
+    // FP64 plain tables: line prefixes per axis, voxel prefix, Dirichlet faces
+    ctx->lltable.clear();
+    for (int axis = 0; axis < 3; ++axis) {
+        ctx->lines_off[axis] = ctx->lltable.size();
+        long long acc = 0;
+        for (int q = 0; q < nsubs; ++q) {
+            ctx->lltable.push_back(acc);
+            acc += ctx->subs[q].vol / ctx->subs[q].n[axis];
+        }
+        ctx->lltable.push_back(acc);
+        ctx->total_lines[axis] = acc;
+    }
+    ctx->vox_off = ctx->lltable.size();
+    {
+        long long acc = 0;
+        for (int q = 0; q < nsubs; ++q) {
+            ctx->lltable.push_back(acc);
+            acc += ctx->subs[q].vol;
+        }
+        ctx->lltable.push_back(acc);
+        ctx->total_vox = acc;
+    }
+    ctx->faces.clear();
+    std::vector<long long> fpre;
+    {
+        long long acc = 0;
+        for (int q = 0; q < nsubs; ++q)
+            for (int f = 0; f < 6; ++f) {
+                if (!((ctx->subs[q].dir_mask >> f) & 1)) continue;
+                const int a = f / 2;
+                const int au = a == 0 ? 1 : 0, aw = a == 2 ? 1 : 2;
+                ctx->faces.push_back(make_int4(q, f, 0, 0));
+                fpre.push_back(acc);
+                acc += (long long)ctx->subs[q].n[au] * ctx->subs[q].n[aw];
+            }
+        fpre.push_back(acc);
+        ctx->total_face = acc;
+    }
+    ctx->face_off = ctx->lltable.size();
+    ctx->lltable.insert(ctx->lltable.end(), fpre.begin(), fpre.end());
+    if (ctx->faces.empty()) ctx->faces.push_back(make_int4(0, 0, 0, 0));
+
+    // cells
+    ctx->cap_total = 0;
+    ctx->comp_total = 0;
+    ctx->stage_cells = 0;
+    ctx->stage_ns = 0;
+    for (SimHost &s : ctx->sims) {
+        s.occ_base = ctx->cap_total;
+        s.comp_base = ctx->comp_total;
+        s.ab_base = ctx->comp_total;
+        ctx->cap_total += s.max_cells + 1;
+        ctx->comp_total += s.max_cells * s.ns;
+        ctx->stage_cells = std::max(ctx->stage_cells, s.max_cells);
+        ctx->stage_ns = std::max(ctx->stage_ns, s.ns);
+    }
+    ctx->key_pad = next_pow2(std::max(ctx->stage_cells, 1));
+
+    // workspace layout
+    size_t w = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = w;
+        w = round_up(w + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    ctx->o_subs = take(sizeof(SubDev) * nsubs);
+    ctx->o_coef32 = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->n_coef32 : 0);
+    ctx->o_coef64 = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->n_coef64 : 0);
+    ctx->o_itable = take(sizeof(int) * ctx->itable.size());
+    ctx->o_lltable = take(sizeof(long long) * ctx->lltable.size());
+    ctx->o_faces = take(sizeof(int4) * ctx->faces.size());
+    ctx->o_cells = take(sizeof(vl::SimCells) * ctx->n_sims);
+    ctx->o_occ_prefix = take(sizeof(int) * (ctx->n_sims + 1));
+    ctx->o_occ_vox = take(sizeof(int) * ctx->cap_total);
+    ctx->o_seg_start = take(sizeof(int) * ctx->cap_total);
+    ctx->o_comp = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->comp_total : 0);
+    ctx->o_ab = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->comp_total : 0);
+    ctx->o_pos = take(sizeof(double) * 3 * ctx->stage_cells);
+    ctx->o_V = take(sizeof(double) * ctx->stage_cells);
+    ctx->o_S = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
+    ctx->o_U = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
+    ctx->o_RS = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
+    ctx->o_keys = take(sizeof(unsigned long long) * ctx->key_pad);
+    ctx->o_seg_id = take(sizeof(int) * ctx->stage_cells);
+    ctx->o_counters = take(sizeof(int) * 4);
+    ctx->o_mass_part = take(sizeof(double) * vl::kMassBlocks);
+    ctx->o_mass_out = take(sizeof(double) * ctx->max_ns);
+    ctx->o_count = take(sizeof(unsigned long long));
+    ctx->ws_bytes = w;
+
+    ctx->finalized = true;
+    if (field_elems) *field_elems = ctx->field_elems;
+    if (workspace_bytes) *workspace_bytes = ctx->ws_bytes;
+    return VL_OK;
+}
+
+int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->finalized) return fail(VL_E_STATE, "call vl_finalize before vl_bind");
+    if (!field_dev || !workspace_dev) return fail(VL_E_ARG, "field and workspace must not be null");
+    if ((reinterpret_cast<uintptr_t>(field_dev) & 255) || (reinterpret_cast<uintptr_t>(workspace_dev) & 255))
+        return fail(VL_E_ARG, "field and workspace must be 256-byte aligned");
+    if (ctx->profiling && !ctx->recs.empty())
+        if (int rc = collect_events(ctx)) return rc;
+    drop_graph(ctx);
+    ctx->field = field_dev;
+    ctx->ws = (char *)workspace_dev;
+    ctx->stream = (hipStream_t)stream;
+    hipStream_t st = ctx->stream;
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_subs, ctx->subs.data(), sizeof(SubDev) * ctx->subs.size(),
+                          hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_itable, ctx->itable.data(), sizeof(int) * ctx->itable.size(),
+                          hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_lltable, ctx->lltable.data(),
+                          sizeof(long long) * ctx->lltable.size(), hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_faces, ctx->faces.data(), sizeof(int4) * ctx->faces.size(),
+                          hipMemcpyHostToDevice, st));
+    VL_HIP(vl::launch_coefficients(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(),
+                                   ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
+                                   ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
+                                   ctx->at<SubDev>(ctx->o_subs), st));
+    ctx->bound = true;
+    if (int rc = upload_cell_tables(ctx)) return rc;
+    VL_HIP(hipStreamSynchronize(st));
+    return VL_OK;
+}
+
+int vl_field_offset(vl_ctx *ctx, int sim, size_t *elem_offset)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->finalized) return fail(VL_E_STATE, "call vl_finalize first");
+    if (!elem_offset) return fail(VL_E_ARG, "elem_offset is null");
+    *elem_offset = ctx->sims[sim].field_off;
+    return VL_OK;
+}
+
+int vl_volume_stride(vl_ctx *ctx, int sim, size_t *elems)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->finalized) return fail(VL_E_STATE, "call vl_finalize first");
+    if (!elems) return fail(VL_E_ARG, "elems is null");
+    *elems = ctx->sims[sim].vol_stride;
+    return VL_OK;
+}
+
+static int field_copy(vl_ctx *ctx, int sim, const void *src, void *dst, int is_device, int layout, int to_field)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    if (layout != VL_SOA && layout != VL_AOS) return fail(VL_E_ARG, "layout must be VL_SOA or VL_AOS");
+    const SimHost &s = ctx->sims[sim];
+    const size_t nv = (size_t)s.nvox(), es = ctx->esize;
+    char *f = (char *)ctx->field + s.field_off * es;
+    hipStream_t st = ctx->stream;
+    if (layout == VL_SOA) {
+        const hipMemcpyKind kind = is_device ? hipMemcpyDeviceToDevice
+                                             : (to_field ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+        for (int q = 0; q < s.ns; ++q) {
+            if (to_field)
+                VL_HIP(hipMemcpyAsync(f + q * s.vol_stride * es, (const char *)src + q * nv * es, nv * es, kind, st));
+            else
+                VL_HIP(hipMemcpyAsync((char *)dst + q * nv * es, f + q * s.vol_stride * es, nv * es, kind, st));
+        }
+    } else if (is_device) {
+        VL_HIP(vl::launch_aos_to_soa(to_field ? src : dst, ctx->field, ctx->precision == VL_F64,
+                                     (long long)s.field_off, (long long)s.vol_stride, (long long)nv, s.ns,
+                                     to_field ? 0 : 1, st));
+    } else {
+        // host AoS: reorder on the host, one copy per substrate
+        std::vector<char> tmp(nv * es);
+        for (int q = 0; q < s.ns; ++q) {
+            if (to_field) {
+                for (size_t v = 0; v < nv; ++v)
+                    std::memcpy(&tmp[v * es], (const char *)src + (v * s.ns + q) * es, es);
+                VL_HIP(hipMemcpyAsync(f + q * s.vol_stride * es, tmp.data(), nv * es, hipMemcpyHostToDevice, st));
+                VL_HIP(hipStreamSynchronize(st));
+            } else {
+                VL_HIP(hipMemcpyAsync(tmp.data(), f + q * s.vol_stride * es, nv * es, hipMemcpyDeviceToHost, st));
+                VL_HIP(hipStreamSynchronize(st));
+                for (size_t v = 0; v < nv; ++v)
+                    std::memcpy((char *)dst + (v * s.ns + q) * es, &tmp[v * es], es);
+            }
+        }
+    }
+    VL_HIP(hipStreamSynchronize(st));
+    return VL_OK;
+}
+
+int vl_set_field(vl_ctx *ctx, int sim, const void *src, int src_is_device, int layout)
+{
+    if (!src) return fail(VL_E_ARG, "src is null");
+    return field_copy(ctx, sim, src, nullptr, src_is_device, layout, 1);
+}
+
+int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout)
+{
+    if (!dst) return fail(VL_E_ARG, "dst is null");
+    return field_copy(ctx, sim, nullptr, dst, dst_is_device, layout, 0);
+}
+
+int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
+                    const double *U, const double *rho_star, int *n_out_of_domain)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    SimHost &s = ctx->sims[sim];
+    if (n < 0) return fail(VL_E_ARG, "n must be >= 0");
+    if (n > s.max_cells)
+        return fail(VL_E_SHAPE, "n exceeds the capacity reserved with vl_reserve_cells (" +
+                                    std::to_string(s.max_cells) + ")");
+    const size_t ns = (size_t)s.ns;
+    if (n > 0) {
+        if (!pos || !V || !S || !U || !rho_star) return fail(VL_E_ARG, "cell arrays must not be null");
+        for (int i = 0; i < n; ++i)
+            if (!(V[i] > 0) || !std::isfinite(V[i])) return fail(VL_E_ARG, "cell volumes must be finite and > 0");
+        for (size_t q = 0; q < (size_t)n * ns; ++q)
+            if (!(S[q] >= 0) || !(U[q] >= 0)) return fail(VL_E_ARG, "rates must be >= 0");
+        if (!finite_all(S, (size_t)n * ns) || !finite_all(U, (size_t)n * ns) ||
+            !finite_all(rho_star, (size_t)n * ns))
+            return fail(VL_E_ARG, "rates and target densities must be finite");
+    }
+    drop_graph(ctx);
+    hipStream_t st = ctx->stream;
+    s.n_cells = n;
+    s.n_occ = 0;
+    s.n_out = 0;
+    if (n == 0) {
+        if (n_out_of_domain) *n_out_of_domain = 0;
+        return upload_cell_tables(ctx);
+    }
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_V, V, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_S, S, sizeof(double) * n * ns, hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_U, U, sizeof(double) * n * ns, hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_RS, rho_star, sizeof(double) * n * ns, hipMemcpyHostToDevice, st));
+    int *counters = ctx->at<int>(ctx->o_counters);
+    VL_HIP(hipMemsetAsync(counters, 0, sizeof(int) * 4, st));
+    const int n_pad = next_pow2(n);
+    unsigned long long *keys = ctx->at<unsigned long long>(ctx->o_keys);
+    VL_HIP(vl::launch_cell_keys(ctx->at<double>(ctx->o_pos), n, s.n[0], s.n[1], s.n[2], s.lo[0], s.lo[1],
+                                s.lo[2], s.h[0], s.h[1], s.h[2], keys, n_pad, counters, st));
+    VL_HIP(vl::launch_bitonic_sort(keys, n_pad, st));
+    int host_counters[4] = {0, 0, 0, 0};
+    VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    VL_HIP(hipStreamSynchronize(st));
+    const int n_out = host_counters[0];
+    const int n_in = n - n_out;
+    int n_occ = 0;
+    if (n_in > 0) {
+        VL_HIP(vl::launch_segments(keys, n_in, ctx->at<int>(ctx->o_seg_id), ctx->at<int>(ctx->o_occ_vox) + s.occ_base,
+                                   ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters + 1, st));
+        VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        VL_HIP(hipStreamSynchronize(st));
+        n_occ = host_counters[1];
+        const double vvox = s.h[0] * s.h[1] * s.h[2];
+        VL_HIP(vl::launch_composites(keys, ctx->at<int>(ctx->o_seg_start) + s.occ_base, n_occ, s.ns,
+                                     ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S),
+                                     ctx->at<double>(ctx->o_U), ctx->at<double>(ctx->o_RS), ctx->dt, vvox,
+                                     ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
+                                     ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_ab) + s.ab_base : nullptr,
+                                     n_in, st));
+    }
+    s.n_occ = n_occ;
+    s.n_out = n_out;
+    if (n_out_of_domain) *n_out_of_domain = n_out;
+    return upload_cell_tables(ctx);
+}
+
+int vl_step(vl_ctx *ctx, int n_steps)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    if (n_steps < 0) return fail(VL_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return VL_OK;
+    if (ctx->profiling || ctx->stream == nullptr) {
+        for (int t = 0; t < n_steps; ++t)
+            if (int rc = enqueue_step(ctx)) return rc;
+        if (ctx->recs.size() > 200000) return collect_events(ctx);
+        return VL_OK;
+    }
+    if (!ctx->graph_valid) {
+        drop_graph(ctx);
+        VL_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_step(ctx);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(VL_E_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+        ctx->graph = g;
+        VL_HIP(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+        ctx->graph_valid = true;
+    }
+    for (int t = 0; t < n_steps; ++t) VL_HIP(hipGraphLaunch(ctx->exec, ctx->stream));
+    return VL_OK;
+}
+
+int vl_sync(vl_ctx *ctx)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    VL_HIP(hipStreamSynchronize(ctx->stream));
+    return VL_OK;
+}
+
+int vl_mass(vl_ctx *ctx, int sim, double *out)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    if (!out) return fail(VL_E_ARG, "out is null");
+    const SimHost &s = ctx->sims[sim];
+    double *outs = ctx->at<double>(ctx->o_mass_out);
+    for (int q = 0; q < s.ns; ++q)
+        VL_HIP(vl::launch_mass(ctx->field, ctx->precision == VL_F64,
+                               (long long)(s.field_off + q * s.vol_stride), s.nvox(),
+                               ctx->at<double>(ctx->o_mass_part), outs + q, ctx->stream));
+    VL_HIP(hipMemcpyAsync(out, outs, sizeof(double) * s.ns, hipMemcpyDeviceToHost, ctx->stream));
+    VL_HIP(hipStreamSynchronize(ctx->stream));
+    return VL_OK;
+}
+
+int vl_check_finite(vl_ctx *ctx, long long *bad)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    unsigned long long *cnt = ctx->at<unsigned long long>(ctx->o_count);
+    VL_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), ctx->stream));
+    VL_HIP(vl::launch_count_nonfinite(ctx->field, ctx->precision == VL_F64, ctx->at<SubDev>(ctx->o_subs),
+                                      (int)ctx->subs.size(), cnt, ctx->stream));
+    unsigned long long h = 0;
+    VL_HIP(hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    VL_HIP(hipStreamSynchronize(ctx->stream));
+    if (bad) *bad = (long long)h;
+    if (h > 0) return fail(VL_E_NONFINITE, std::to_string(h) + " non-finite field values");
+    return VL_OK;
+}
+
+int vl_set_profiling(vl_ctx *ctx, int enable)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!enable && !ctx->recs.empty())
+        if (int rc = collect_events(ctx)) return rc;
+    if (enable && !ctx->profiling)
+        for (int k = 0; k < VL_K_COUNT; ++k) {
+            ctx->k_launches[k] = 0;
+            ctx->k_ms[k] = 0.0;
+        }
+    ctx->profiling = enable != 0;
+    return VL_OK;
+}
+
+int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (kind < 0 || kind >= VL_K_COUNT) return fail(VL_E_ARG, "unknown kernel kind");
+    if (int rc = collect_events(ctx)) return rc;
+    if (launches) *launches = ctx->k_launches[kind];
+    if (total_ms) *total_ms = ctx->k_ms[kind];
+    return VL_OK;
+}
+
+}  // extern "C"

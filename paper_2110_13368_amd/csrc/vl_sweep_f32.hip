@@ -1,0 +1,377 @@
+// vl_sweep_f32.hip -- FP32 line solves of the LOD step for gfx950.
+//
+// arXiv:2110.13368, section "Elements of Parallelism": the implicit
+// diffusion-decay update is solved direction by direction (x, then y, then z),
+// every grid line of every substrate being a constant-coefficient tridiagonal
+// system solved by elimination (the paper's axpy) and back-substitution (its
+// naxpy); Dirichlet conditions are applied by their own function around the
+// solves.  Here the Dirichlet projection and the decay factor are folded into
+// the solve's loads and stores, so each sweep reads and writes every element
+// once.
+//
+// Split solve.  The line matrix T = tridiag(-c, b, -c) has the same end
+// diagonal at both ends, so it is persymmetric: eliminating from the last row
+// upwards meets the same pivots d_t as eliminating from the first row
+// downwards.  A line of n rows is split at its middle row m = (n-1)/2:
+//   wave 0 eliminates rows 0..m-1 downwards   y_t = r_t/d_t + (c/d_t) y_{t-1}
+//   wave 1 eliminates rows n-1..m+1 upwards   z_t likewise, from the other end
+//   the middle row gives x_m = (r_m + c y_{m-1} + c z_{m+1}) / gamma
+//   both waves back-substitute outwards       x_t = y_t + (c/d_t) x_{t+1}.
+// This is Gaussian elimination without pivoting on a reordered system (an
+// exact factorisation, as is the plain Thomas algorithm); both waves use the
+// same pivot table, indexed by the distance from their end.
+//
+// Mapping.  A workgroup is two waves and owns a tile of 64 lines; lane l of
+// both waves works on line l.  Each wave walks its rows in one direction with
+// a wave-uniform row offset, so y- and z-lines (stride nx, nx*ny) are read and
+// written as 256-byte rows of 64 neighbouring x values.  x-lines are
+// contiguous: they are moved through a 64x65 LDS block per 64 columns, loaded
+// with lanes along x and read back with lanes along the lines.  The half line
+// a lane owns stays in VGPRs (CAP values).
+#include "vl_internal.h"
+
+namespace vl {
+
+// Workgroup b runs on XCD b % 8; give each XCD a contiguous range of tiles so
+// that tiles sharing cache lines meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb)
+{
+    const int x = bid & 7, q = bid >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return (x < rem) ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+}
+
+// Largest k in [0, count) with prefix[k] <= tile.
+__device__ __forceinline__ int find_slot(const int *__restrict__ prefix, int count, int tile)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Highest-numbered face whose bit is set in both masks, -1 if none.
+__device__ __forceinline__ int top_face(int mask)
+{
+    return mask ? 31 - __builtin_clz(mask) : -1;
+}
+
+__device__ __forceinline__ float face_value(const float (&d)[6], int f)
+{
+    float v = d[0];
+    v = (f == 1) ? d[1] : v;
+    v = (f == 2) ? d[2] : v;
+    v = (f == 3) ? d[3] : v;
+    v = (f == 4) ? d[4] : v;
+    v = (f == 5) ? d[5] : v;
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Raw buffer access: the lane part of an offset stays in a VGPR, the
+// wave-uniform row part goes in an SGPR, so walking a line costs no vector
+// address arithmetic.  Offsets are in bytes from the resource base.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float *base, long long elems)
+{
+    const long long bytes = elems * 4;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0,
+                                             (int)min(bytes, (long long)0x7fffffff), 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
+}
+
+// Runs BODY for t = 0..CAP-1 with t < cnt, cnt wave-uniform: whole groups
+// of 8 without per-element tests.  Written as macros so that every register
+// index is a constant after unrolling (the array must never leave VGPRs).
+#define VL_FOR_UP(CAP_, cnt, t, BODY)                                                  \
+    _Pragma("unroll") for (int g_ = 0; g_ < (CAP_); g_ += 8)                           \
+    {                                                                                  \
+        if (g_ + 8 <= (cnt)) {                                                         \
+            _Pragma("unroll") for (int j_ = 0; j_ < 8; ++j_)                           \
+            {                                                                          \
+                const int t = g_ + j_;                                                 \
+                if (t < (CAP_)) { BODY }                                               \
+            }                                                                          \
+        } else if (g_ < (cnt)) {                                                       \
+            _Pragma("unroll") for (int j_ = 0; j_ < 8; ++j_)                           \
+            {                                                                          \
+                const int t = g_ + j_;                                                 \
+                if (t < (CAP_) && t < (cnt)) { BODY }                                  \
+            }                                                                          \
+        }                                                                              \
+    }
+// Same, t descending.
+#define VL_FOR_DOWN(CAP_, cnt, t, BODY)                                                \
+    _Pragma("unroll") for (int g_ = ((CAP_) + 7) / 8 * 8 - 8; g_ >= 0; g_ -= 8)        \
+    {                                                                                  \
+        if (g_ + 8 <= (cnt)) {                                                         \
+            _Pragma("unroll") for (int j_ = 7; j_ >= 0; --j_)                          \
+            {                                                                          \
+                const int t = g_ + j_;                                                 \
+                if (t < (CAP_)) { BODY }                                               \
+            }                                                                          \
+        } else if (g_ < (cnt)) {                                                       \
+            _Pragma("unroll") for (int j_ = 7; j_ >= 0; --j_)                          \
+            {                                                                          \
+                const int t = g_ + j_;                                                 \
+                if (t < (CAP_) && t < (cnt)) { BODY }                                  \
+            }                                                                          \
+        }                                                                              \
+    }
+
+template <int AXIS, int CAP>
+__global__ void __launch_bounds__(128)
+sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
+          float *__restrict__ field)
+{
+    constexpr int kChunks = (CAP + 63) / 64;
+    constexpr int kStage = (AXIS == 0) ? 2 * 64 * 65 : 1;
+    __shared__ float xch[2][kWave];
+    __shared__ float2 cs_lds[CAP];
+    __shared__ float stage[kStage];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int slot = find_slot(L.tile_prefix, L.count, tile);
+    const int local = tile - L.tile_prefix[slot];
+    const SubDev &S = subs[L.sub_ids[slot]];
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const bool top = (wave == 0);
+
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int n = S.n[AXIS];
+    const int m = (n - 1) >> 1;    // middle row
+    const int cb = n - 1 - m;      // rows below the middle (m or m + 1)
+    const int nel = top ? m : cb;  // rows this wave eliminates and holds
+    const float g1 = S.mid32[AXIS][0];
+    const float g2 = S.mid32[AXIS][1];
+    const int dmask = S.dir_mask;
+
+    // pivot table (inv_d_t, c/d_t), t < cb, staged once per workgroup
+    {
+        const float2 *__restrict__ cf = coef + S.coef32[AXIS];
+        for (int t = threadIdx.x; t < cb && t < CAP; t += 128) cs_lds[t] = cf[t];
+    }
+
+    // Geometry of this lane's line: faces of the other axes it lies on, and a
+    // buffer resource plus offsets to address its rows.
+    int on = 0;
+    long long base = 0;      // element offset of the resource base
+    unsigned lane_b = 0;     // per-lane byte offset (y, z: along x; x: row start)
+    int row_b = 0;           // bytes between rows (y, z) / between x-lines (x)
+    int xrows_left = 0;      // x-lines of the tile that exist
+    if (AXIS == 0) {
+        const int nrows = ny * nz;
+        const int r0 = local * kTileLines;
+        const int r = min(r0 + lane, nrows - 1);
+        const int j = r % ny, k = r / ny;
+        on = (j == 0 ? 1 << 2 : 0) | (j == ny - 1 ? 1 << 3 : 0) |
+             (k == 0 ? 1 << 4 : 0) | (k == nz - 1 ? 1 << 5 : 0);
+        base = S.base + (long long)r0 * nx;
+        lane_b = (unsigned)(r - r0) * (unsigned)nx * 4u;
+        row_b = nx * 4;
+        xrows_left = nrows - r0;
+    } else {
+        const int nxb = (nx + kTileLines - 1) / kTileLines;
+        const int xb = local % nxb;
+        const int o = local / nxb;
+        const int i = min(xb * kTileLines + lane, nx - 1);
+        on = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0);
+        if (AXIS == 1) {
+            on |= (o == 0 ? 1 << 4 : 0) | (o == nz - 1 ? 1 << 5 : 0);
+            base = S.base + (long long)o * nx * ny + xb * kTileLines;
+            row_b = nx * 4;
+        } else {
+            on |= (o == 0 ? 1 << 2 : 0) | (o == ny - 1 ? 1 << 3 : 0);
+            base = S.base + (long long)o * nx + xb * kTileLines;
+            row_b = nx * ny * 4;
+        }
+        lane_b = (unsigned)(i - xb * kTileLines) * 4u;
+    }
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(field + base, S.base + S.vol - base);
+    const int wface = top_face(dmask & on);  // whole line Dirichlet
+    const int lo_f = (dmask >> (2 * AXIS)) & 1 ? 2 * AXIS : -1;
+    const int hi_f = (dmask >> (2 * AXIS + 1)) & 1 ? 2 * AXIS + 1 : -1;
+    const int f_first = max(wface, max(lo_f, n == 1 ? hi_f : -1));  // row 0
+    const int f_last = max(wface, hi_f);                            // row n-1
+
+    float v[CAP];
+
+    // ---- load the half line (local t: wave 0 row t, wave 1 row n-1-t) ----
+    if (AXIS == 0) {
+        float *st = stage + wave * 64 * 65;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            if (c * 64 < nel) {
+                const int cs = top ? c * 64 : n - 64 * (c + 1);
+                const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
+                const int so = col - cs;
+                const unsigned cb4 = (unsigned)col * 4u;
+#pragma unroll 16
+                for (int q = 0; q < 64; ++q)
+                    st[q * 65 + so] = bload(rs, cb4, min(q, xrows_left - 1) * row_b);
+                wave_sync_lds();
+                if (top) {
+#pragma unroll
+                    for (int jj = 0; jj < 64; ++jj)
+                        if (c * 64 + jj < CAP && c * 64 + jj < nel) v[c * 64 + jj] = st[lane * 65 + jj];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < 64; ++jj)
+                        if (c * 64 + jj < CAP && c * 64 + jj < nel) v[c * 64 + jj] = st[lane * 65 + 63 - jj];
+                }
+                wave_sync_lds();
+            }
+        }
+    } else {
+        const int row0 = top ? 0 : (n - 1) * row_b;
+        const int step = top ? row_b : -row_b;
+        VL_FOR_UP(CAP, nel, t, v[t] = bload(rs, lane_b, row0 + t * step);)
+    }
+
+    __syncthreads();  // pivot table visible
+
+    // ---- Dirichlet projection before the x solve: only the end rows matter,
+    //      whole-line Dirichlet lines are overwritten after the solve ----
+    if (AXIS == 0) {
+        if (!top && cb >= 1 && hi_f >= 0) v[0] = S.dval32[hi_f];
+        if (top && m >= 1 && lo_f >= 0) v[0] = S.dval32[lo_f];
+    }
+
+    // ---- elimination from this wave's end towards the middle ----
+    float prev = 0.f;
+    VL_FOR_UP(CAP, nel, t, {
+        const float2 c = cs_lds[t];
+        prev = fmaf(c.y, prev, v[t] * c.x);
+        v[t] = prev;
+    })
+
+    // ---- middle row ----
+    float xm = 0.f;
+    if (!top) xch[0][lane] = prev;  // z_{m+1} (0 when the line has one row)
+    __syncthreads();
+    if (top) {
+        float rm;
+        if (AXIS == 0) {
+            rm = bload(rs, lane_b + (unsigned)m * 4u, 0);
+            if (m == 0) {
+                const int f0 = max(lo_f, n == 1 ? hi_f : -1);
+                if (f0 >= 0) rm = S.dval32[f0];
+            }
+        } else {
+            rm = bload(rs, lane_b, m * row_b);
+        }
+        xm = fmaf(g2, prev + xch[0][lane], rm * g1);
+        xch[1][lane] = xm;
+    }
+    __syncthreads();
+    if (!top) xm = xch[1][lane];
+
+    // ---- back-substitution from the middle outwards ----
+    float nxt = xm;
+    VL_FOR_DOWN(CAP, nel, t, {
+        nxt = fmaf(cs_lds[t].y, nxt, v[t]);
+        v[t] = nxt;
+    })
+
+    // ---- Dirichlet projection after the solve ----
+    if (__builtin_amdgcn_ballot_w64(wface >= 0) != 0) {
+        const float wv = face_value(S.dval32, wface);
+        const bool whole = wface >= 0;
+        VL_FOR_UP(CAP, nel, t, v[t] = whole ? wv : v[t];)
+        xm = whole ? wv : xm;
+    }
+    if (top) {
+        if (f_first >= 0) {
+            const float ev = face_value(S.dval32, f_first);
+            if (m >= 1)
+                v[0] = ev;
+            else
+                xm = ev;
+        }
+    } else if (cb >= 1 && f_last >= 0) {
+        v[0] = face_value(S.dval32, f_last);
+    }
+
+    // ---- store ----
+    if (AXIS == 0) {
+        float *st = stage + wave * 64 * 65;
+        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm);
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            if (c * 64 < nel) {
+                if (top) {
+#pragma unroll
+                    for (int jj = 0; jj < 64; ++jj)
+                        if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + jj] = v[c * 64 + jj];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < 64; ++jj)
+                        if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + 63 - jj] = v[c * 64 + jj];
+                }
+                wave_sync_lds();
+                const int cs = top ? c * 64 : n - 64 * (c + 1);
+                const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
+                const int so = col - cs;
+                const unsigned cb4 = (unsigned)col * 4u;
+#pragma unroll 16
+                for (int q = 0; q < 64; ++q)
+                    if (q < xrows_left) bstore(rs, cb4, q * row_b, st[q * 65 + so]);
+                wave_sync_lds();
+            }
+        }
+    } else {
+        if (top) bstore(rs, lane_b, m * row_b, xm);
+        const int row0 = top ? 0 : (n - 1) * row_b;
+        const int step = top ? row_b : -row_b;
+        VL_FOR_UP(CAP, nel, t, bstore(rs, lane_b, row0 + t * step, v[t]);)
+    }
+}
+
+template <int AXIS>
+static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *subs,
+                              const float2 *coef, float *field, hipStream_t st)
+{
+    const dim3 grid(L.total_tiles), block(128);
+    switch (cap_idx) {
+    case 0: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[0]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 1: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[1]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 2: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[2]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 3: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[3]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 4: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 5: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 6: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, field); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,
+                            const float2 *coef, float *field, hipStream_t st)
+{
+    if (L.total_tiles <= 0) return hipSuccess;
+    if (axis == 0) return launch_axis<0>(cap_idx, L, subs, coef, field, st);
+    if (axis == 1) return launch_axis<1>(cap_idx, L, subs, coef, field, st);
+    if (axis == 2) return launch_axis<2>(cap_idx, L, subs, coef, field, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace vl

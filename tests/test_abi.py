@@ -1,0 +1,106 @@
+"""The C ABI of libvoxlod.so without a GPU: the library loads, exports every
+function include/voxlod.h declares, and rejects bad arguments on the host
+before anything reaches the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2110_13368_amd import binding as vb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "voxlod.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vl_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = C.CDLL(vb.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(vb.SIGNATURES)
+
+
+def test_abi_version():
+    assert vb.vl_abi_version() == 1
+
+
+def _code(fn, *args):
+    with pytest.raises(vb.VoxlodError) as e:
+        fn(*args)
+    return e.value.code
+
+
+def test_create_rejects_bad_arguments():
+    assert _code(vb.vl_create, 0) == vb.VL_E_ARG
+    assert _code(vb.vl_create, 1, 7) == vb.VL_E_ARG
+    assert _code(vb.vl_create, 1, vb.VL_F32, 9) == vb.VL_E_ARG
+    assert "precision" in vb.vl_last_error() or "decay" in vb.vl_last_error()
+
+
+def test_setup_validation_and_sizes():
+    h = vb.vl_create(2, vb.VL_F32)
+    try:
+        assert _code(vb.vl_set_grid, h, 2, 4, 4, 4, 1, 1, 1, 0, 0, 0) == vb.VL_E_ARG  # sim index
+        assert _code(vb.vl_set_grid, h, 0, 0, 4, 4, 1, 1, 1, 0, 0, 0) == vb.VL_E_ARG
+        assert _code(vb.vl_set_grid, h, 0, 4, 4, 4, -1, 1, 1, 0, 0, 0) == vb.VL_E_ARG
+        assert _code(vb.vl_set_grid, h, 0, 4, 4, 4, 1, float("nan"), 1, 0, 0, 0) == vb.VL_E_ARG
+        assert _code(vb.vl_set_grid, h, 0, 1024, 1024, 1024, 1, 1, 1, 0, 0, 0) == vb.VL_E_SHAPE
+        assert _code(vb.vl_finalize, h, 0.01) == vb.VL_E_STATE  # no grid yet
+        vb.vl_set_grid(h, 0, 50, 40, 30, 20, 20, 20, -500, -400, -300)
+        vb.vl_set_grid(h, 1, 7, 1, 3, 10, 10, 10, 0, 0, 0)
+        assert _code(vb.vl_set_boundary, h, 0, 0, 0, vb.VL_DIRICHLET, 1.0) == vb.VL_E_ARG  # no substrates
+        assert _code(vb.vl_set_substrates, h, 0, [1.0, -2.0], [0.0, 0.0]) == vb.VL_E_ARG
+        vb.vl_set_substrates(h, 0, [1e5, 1e3], [0.1, 0.0])
+        vb.vl_set_substrates(h, 1, [5e4], [1.0])
+        assert _code(vb.vl_set_boundary, h, 0, 0, 6, vb.VL_DIRICHLET, 1.0) == vb.VL_E_ARG
+        assert _code(vb.vl_set_boundary, h, 0, 2, 0, vb.VL_DIRICHLET, 1.0) == vb.VL_E_ARG
+        assert _code(vb.vl_set_boundary, h, 0, 0, 0, 3, 1.0) == vb.VL_E_ARG
+        assert _code(vb.vl_set_boundary, h, 0, 0, 0, vb.VL_DIRICHLET, float("inf")) == vb.VL_E_ARG
+        vb.vl_set_boundary(h, 0, 1, 5, vb.VL_DIRICHLET, 38.0)
+        assert _code(vb.vl_reserve_cells, h, 0, -1) == vb.VL_E_ARG
+        assert _code(vb.vl_reserve_cells, h, 0, (1 << 24) + 1) == vb.VL_E_ARG
+        vb.vl_reserve_cells(h, 0, 1000)
+        assert _code(vb.vl_finalize, h, 0.0) == vb.VL_E_ARG
+        assert _code(vb.vl_step, h, 1) == vb.VL_E_STATE
+        assert _code(vb.vl_bind, h, 0, 0, 0) == vb.VL_E_STATE  # not finalized
+        fe, wb = vb.vl_finalize(h, 0.01)
+        # volumes are padded to 64 floats (256 bytes)
+        vol0 = -(-50 * 40 * 30 // 64) * 64
+        vol1 = -(-7 * 1 * 3 // 64) * 64
+        assert fe == 2 * vol0 + vol1
+        assert vb.vl_field_offset(h, 1) == 2 * vol0
+        assert vb.vl_volume_stride(h, 0) == vol0
+        assert wb > 0 and wb % 256 == 0
+        assert _code(vb.vl_finalize, h, 0.01) == vb.VL_E_STATE
+        assert _code(vb.vl_set_grid, h, 0, 4, 4, 4, 1, 1, 1, 0, 0, 0) == vb.VL_E_STATE
+        assert _code(vb.vl_bind, h, 0, 0, 0) == vb.VL_E_ARG  # null buffers
+        assert _code(vb.vl_bind, h, 256, 4, 0) == vb.VL_E_ARG  # misaligned
+        assert _code(vb.vl_step, h, 1) == vb.VL_E_STATE  # not bound
+        assert _code(vb.vl_upload_cells, h, 0, [[0, 0, 0]], [1.0], [[1, 1]], [[1, 1]], [[1, 1]], 2) == vb.VL_E_STATE
+    finally:
+        vb.vl_destroy(h)
+
+
+def test_fp32_rejects_overlong_lines_fp64_accepts():
+    for precision, expect in ((vb.VL_F32, vb.VL_E_SHAPE), (vb.VL_F64, None)):
+        h = vb.vl_create(1, precision)
+        try:
+            vb.vl_set_grid(h, 0, 600, 2, 2, 1, 1, 1, 0, 0, 0)
+            vb.vl_set_substrates(h, 0, [1.0], [0.0])
+            if expect is None:
+                vb.vl_finalize(h, 0.01)
+            else:
+                assert _code(vb.vl_finalize, h, 0.01) == expect
+        finally:
+            vb.vl_destroy(h)
+
+
+def test_destroy_null_is_ok():
+    vb.vl_destroy(None)

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances: the plain FP64 path must agree to 1e-12 relative; the FP32 path
+to 1e-5 relative in both the max norm and the L2 norm per substrate, the
+accuracy target set for FP32 storage and sweeps over 100 steps.  The paper's
+own Method 2 (section "Methods of Validation") is this voxel-by-voxel
+cross-check of the GPU field against the CPU field.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2110_13368_amd import binding as vb
+from paper_2110_13368_amd import workloads as W
+from tests.gpu_helpers import assert_close, rel_errs, run_gpu, run_oracle, subset
+
+pytestmark = pytest.mark.gpu
+
+DECAYS = [(vb.VL_DECAY_ONCE, O.DECAY_ONCE), (vb.VL_DECAY_THIRDS, O.DECAY_THIRDS)]
+
+
+def _spec(shape, n_sub, bc, n_cells, dtype, seed, layout="uniform", h=(20.0, 20.0, 20.0)):
+    rng = np.random.default_rng(W.SEED_BASE + 500 + seed)
+    spec = W.make_sim(rng, shape, h, n_sub, dtype=dtype, bc=bc, n_cells=n_cells, cell_layout=layout,
+                      sigma=0.25 * min(n * d for n, d in zip(shape, h)))
+    if n_cells >= 3:
+        spec.cells.pos[1] = spec.cells.pos[0]          # two cells in one voxel
+        spec.cells.pos[2] = np.array(spec.lo) - 3.0    # one cell outside the grid
+    return spec
+
+
+# --------------------------------------------------------------------------
+# plain FP64 path
+
+def test_fp64_plain_configuration():
+    """50^3 voxels, Dirichlet 38 on every face, 1000 uptake-only cells, 100 steps."""
+    wl = W.plain_fp64()
+    spec = wl.sims[0]
+    (got,), _ = run_gpu([spec], wl.steps, precision=vb.VL_F64)
+    want = run_oracle(spec, wl.steps)
+    assert_close(got, want, 1e-12, "plain 50^3")
+    assert np.max(got) <= 38.0 + 1e-9 and np.min(got) > 0.0
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3), (1, 1, 6), (6, 1, 1), (1, 5, 1), (2, 3, 4), (1, 1, 1), (9, 8, 7)])
+@pytest.mark.parametrize("bc", ["neumann", "dirichlet", "mixed"])
+@pytest.mark.parametrize("decay", DECAYS)
+def test_fp64_tiny_grids(shape, bc, decay):
+    spec = _spec(shape, 2, bc, 9, "f64", hash((shape, bc)) % 1000)
+    (got,), n_out = run_gpu([spec], 3, precision=vb.VL_F64, decay=decay[0])
+    want = run_oracle(spec, 3, decay[1])
+    assert n_out == [1]
+    assert_close(got, want, 1e-12, f"fp64 {shape} {bc}")
+
+
+# --------------------------------------------------------------------------
+# FP32 path: line lengths around every split and capacity boundary
+
+LINE_LENGTHS = [1, 2, 3, 4, 5, 63, 64, 65, 66, 127, 128, 129, 130, 131, 193, 257, 258, 321, 401, 513]
+
+
+@pytest.mark.parametrize("n", LINE_LENGTHS)
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_fp32_line_lengths(n, axis):
+    shape = [3, 5, 2]
+    shape[axis] = n
+    spec = _spec(tuple(shape), 2, "mixed", 12, "f32", n * 3 + axis)
+    (got,), _ = run_gpu([spec], 20)
+    want = run_oracle(spec, 20)
+    assert_close(got, want, 1e-5, f"fp32 n={n} axis={axis}")
+
+
+@pytest.mark.parametrize("decay", DECAYS)
+@pytest.mark.parametrize("bc", ["neumann", "dirichlet", "mixed"])
+def test_fp32_boundary_mixes_and_decay(bc, decay):
+    spec = _spec((33, 70, 19), 3, bc, 400, "f32", 11, layout="gaussian")
+    (got,), _ = run_gpu([spec], 30, decay=decay[0])
+    want = run_oracle(spec, 30, decay[1])
+    assert_close(got, want, 1e-5, f"fp32 {bc}")
+
+
+def test_fp32_single_large_scaled_100_steps():
+    """The single large simulation at a quarter of its edge (50^3 x 4, Gaussian
+    ball of cells), 100 steps."""
+    wl = W.single_large(scale=0.25)
+    spec = wl.sims[0]
+    (got,), _ = run_gpu([spec], 100)
+    want = run_oracle(spec, 100)
+    errs = assert_close(got, want, 1e-5, "single-large/4")
+    print("single-large/4 errors per substrate (max, L2):", errs)
+
+
+def test_fp32_batched_ragged():
+    wl = W.batched(n_sims=6, edge_range=(7, 70), cells_range=(50, 800))
+    fields, n_out = run_gpu(wl.sims, 40)
+    assert n_out == [0] * 6
+    for k, spec in enumerate(wl.sims):
+        assert_close(fields[k], run_oracle(spec, 40), 1e-5, f"batch sim {k} {spec.shape}")
+
+
+def test_fp64_batched_ragged():
+    wl = W.batched(n_sims=4, edge_range=(5, 40), cells_range=(20, 300), dtype="f64")
+    fields, _ = run_gpu(wl.sims, 10, precision=vb.VL_F64)
+    for k, spec in enumerate(wl.sims):
+        assert_close(fields[k], run_oracle(spec, 10), 1e-12, f"fp64 batch sim {k}")
+
+
+def test_fp32_many_cells_in_one_voxel():
+    spec = _spec((16, 16, 16), 2, "neumann", 0, "f32", 5)
+    n = 300
+    rng = np.random.default_rng(9)
+    pos = np.tile(np.array([[1.0, 2.0, 3.0]]), (n, 1))
+    V, S, U, rs = W.tumour_rates(rng, n, 2)
+    spec.cells = W.Cells(pos, V, S, U, rs)
+    (got,), _ = run_gpu([spec], 5)
+    assert_close(got, run_oracle(spec, 5), 1e-5, "300 cells in one voxel")
+
+
+def test_all_cells_outside():
+    spec = _spec((8, 8, 8), 1, "mixed", 5, "f32", 6)
+    spec.cells.pos[:] = np.array(spec.lo) - 10.0
+    (got,), n_out = run_gpu([spec], 4)
+    assert n_out == [5]
+    assert_close(got, run_oracle(spec, 4), 1e-5, "cells outside")
+
+
+# --------------------------------------------------------------------------
+# determinism, graph replay, diagnostics
+
+def test_bitwise_repeatable_and_graph_equals_direct():
+    spec = _spec((40, 37, 29), 2, "mixed", 500, "f32", 21)
+    (a,), _ = run_gpu([spec], 25)
+    (b,), _ = run_gpu([spec], 25)
+    (c,), _ = run_gpu([spec], 25, profiling=True)  # direct launches with events
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+def test_batch_of_one_equals_single():
+    wl = W.batched(n_sims=3, edge_range=(10, 40), cells_range=(50, 200))
+    fields, _ = run_gpu(wl.sims, 7)
+    (alone,), _ = run_gpu([wl.sims[1]], 7)
+    assert np.array_equal(fields[1], alone)
+
+
+@pytest.mark.parametrize("precision", [vb.VL_F32, vb.VL_F64])
+def test_mass_and_nonfinite(precision):
+    spec = _spec((30, 20, 10), 3, "neumann", 0, "f32" if precision == vb.VL_F32 else "f64", 31)
+    spec.lam[:] = 0.0
+    ctx = vb.Context([spec], precision=precision)
+    try:
+        m0 = ctx.mass(0)
+        np.testing.assert_allclose(m0, spec.rho0.astype(np.float64).reshape(3, -1).sum(axis=1), rtol=1e-12)
+        ctx.step(50)
+        m1 = ctx.mass(0)
+        field = ctx.get_field(0).astype(np.float64)
+        np.testing.assert_allclose(m1, field.reshape(3, -1).sum(axis=1), rtol=1e-12)
+        # zero flux and no decay: mass is conserved up to the storage precision
+        tol = 2e-5 if precision == vb.VL_F32 else 1e-12
+        np.testing.assert_allclose(m1, m0, rtol=tol)
+        assert ctx.check_finite() == 0
+        bad = field.copy()
+        bad[1, 3, 4, 5] = np.nan
+        bad[2, 0, 0, 0] = np.inf
+        ctx.set_field(0, bad)
+        assert ctx.check_finite() == 2
+    finally:
+        ctx.close()
+
+
+def test_device_field_io_and_aos():
+    spec = _spec((11, 9, 7), 3, "mixed", 30, "f32", 41)
+    ctx = vb.Context([spec])
+    try:
+        import torch
+        view = ctx.field_view(0)
+        assert torch.equal(view.cpu(), torch.from_numpy(spec.rho0))
+        aos = np.ascontiguousarray(np.moveaxis(spec.rho0, 0, -1))
+        out = np.empty_like(aos)
+        vb.vl_get_field(ctx.h, 0, out.ctypes.data, False, vb.VL_AOS)
+        assert np.array_equal(out, aos)
+        dev = torch.from_numpy(aos).cuda()
+        ctx.step(2)
+        vb.vl_set_field(ctx.h, 0, dev.data_ptr(), True, vb.VL_AOS)
+        assert np.array_equal(ctx.get_field(0), spec.rho0)
+    finally:
+        ctx.close()
+
+
+# --------------------------------------------------------------------------
+# full-size configurations, in the launch shape the benchmark times, checked
+# on sampled substrates (substrates are independent) or sampled simulations
+
+def test_full_single_large_sampled():
+    wl = W.single_large()
+    spec = wl.sims[0]
+    (got,), _ = run_gpu([spec], 3)
+    for s in (0, 3):
+        want = run_oracle(subset(spec, [s]), 3)
+        assert_close(got[s:s + 1], want, 1e-5, f"200^3 substrate {s}")
+
+
+def test_full_tumour_scale_sampled():
+    wl = W.tumour_scale()
+    spec = wl.sims[0]
+    (got,), _ = run_gpu([spec], 2)
+    s = int(np.argmax(spec.D))  # the widest stencil coupling
+    want = run_oracle(subset(spec, [s]), 2)
+    assert_close(got[s:s + 1], want, 1e-5, f"400^3 substrate {s}")
+
+
+def test_full_batched_sampled():
+    wl = W.batched()
+    fields, n_out = run_gpu(wl.sims, 3)
+    assert sum(n_out) == 0
+    sizes = [int(np.prod(s.shape)) for s in wl.sims]
+    for k in (int(np.argmin(sizes)), int(np.argmax(sizes)), 17):
+        assert_close(fields[k], run_oracle(wl.sims[k], 3), 1e-5, f"batch sim {k} {wl.sims[k].shape}")
