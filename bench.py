@@ -68,6 +68,26 @@ def kernel_profile(ctx, steps: int):
     return stats
 
 
+def copy_reference(nbytes: int, reps: int = 20):
+    """Device-to-device copy of nbytes with a plain elementwise kernel: the
+    practical bandwidth ceiling, and the kernel of known traffic (nbytes read,
+    nbytes written per launch) that scales the FETCH_SIZE / WRITE_SIZE
+    counters."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "GBps_read_plus_write": round(2 * nbytes / t / 1e9, 1)}
+
+
 def cpu_baseline(wl, budget_s: float):
     """The FP64 oracle on the host cores: whole steps of the same workload
     (for a batch: its first simulations), as many as fit the time budget."""
@@ -99,6 +119,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-reference", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -186,6 +207,8 @@ def main():
         "kernels": kernels,
     }
     line.update(extra)
+    if not args.no_copy_reference:
+        line["copy_reference"] = [copy_reference(128 << 20), copy_reference(2 << 30, reps=5)]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -495,14 +495,9 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
                 for (int q : groups[ci]) {
                     ctx->itable.push_back((int)acc);
                     const SubDev &d = ctx->subs[q];
-                    const long long nxb = (d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
-                    long long tiles;
-                    if (axis == 0)
-                        tiles = ((long long)d.n[1] * d.n[2] + vl::kTileLines - 1) / vl::kTileLines;
-                    else if (axis == 1)
-                        tiles = nxb * d.n[2];
-                    else
-                        tiles = nxb * d.n[1];
+                    // lines of this axis, 64 consecutive lines per tile
+                    const long long lines = d.vol / d.n[axis];
+                    const long long tiles = (lines + vl::kTileLines - 1) / vl::kTileLines;
                     acc += tiles;
                     if (acc >= (1ll << 31)) return fail(VL_E_SHAPE, "too many tiles in one launch");
                 }

@@ -136,6 +136,12 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
         }                                                                              \
     }
 
+// Waves per SIMD the register budget is sized for, by capacity class.
+__host__ __device__ constexpr int waves_for_cap(int cap)
+{
+    return cap <= 64 ? 4 : cap <= 128 ? 3 : cap <= 200 ? 2 : 1;
+}
+
 template <int AXIS, int CAP>
 __global__ void __launch_bounds__(128)
 sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
@@ -190,21 +196,28 @@ sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restri
         row_b = nx * 4;
         xrows_left = nrows - r0;
     } else {
-        const int nxb = (nx + kTileLines - 1) / kTileLines;
-        const int xb = local % nxb;
-        const int o = local / nxb;
-        const int i = min(xb * kTileLines + lane, nx - 1);
+        // y-lines (i, k) and z-lines (i, j) numbered L = i + nx*o; a tile is 64
+        // consecutive lines, so no lane idles except in a volume's last tile.
+        const int no = (AXIS == 1) ? nz : ny;
+        const int nlines = nx * no;
+        const int L0 = local * kTileLines;
+        const int L = min(L0 + lane, nlines - 1);
+        const int i = L % nx, o = L / nx;
         on = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0);
+        long long start, start0;
         if (AXIS == 1) {
             on |= (o == 0 ? 1 << 4 : 0) | (o == nz - 1 ? 1 << 5 : 0);
-            base = S.base + (long long)o * nx * ny + xb * kTileLines;
+            start = i + (long long)o * nx * ny;
+            start0 = (L0 % nx) + (long long)(L0 / nx) * nx * ny;
             row_b = nx * 4;
         } else {
             on |= (o == 0 ? 1 << 2 : 0) | (o == ny - 1 ? 1 << 3 : 0);
-            base = S.base + (long long)o * nx + xb * kTileLines;
+            start = L;
+            start0 = L0;
             row_b = nx * ny * 4;
         }
-        lane_b = (unsigned)(i - xb * kTileLines) * 4u;
+        base = S.base + start0;
+        lane_b = (unsigned)(start - start0) * 4u;
     }
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(field + base, S.base + S.vol - base);
     const int wface = top_face(dmask & on);  // whole line Dirichlet
@@ -223,11 +236,15 @@ sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restri
             if (c * 64 < nel) {
                 const int cs = top ? c * 64 : n - 64 * (c + 1);
                 const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
-                const int so = col - cs;
                 const unsigned cb4 = (unsigned)col * 4u;
-#pragma unroll 16
+                // DMA straight into LDS: lane j's value of row q lands in
+                // st[q*65 + j]; no VGPR staging, all 64 rows in flight.
+#pragma unroll
                 for (int q = 0; q < 64; ++q)
-                    st[q * 65 + so] = bload(rs, cb4, min(q, xrows_left - 1) * row_b);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (__attribute__((address_space(3))) void *)(st + q * 65), 4, (int)cb4,
+                        min(q, xrows_left - 1) * row_b, 0, 0);
+                __builtin_amdgcn_s_waitcnt(0);
                 wave_sync_lds();
                 if (top) {
 #pragma unroll
