@@ -124,7 +124,8 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
 
 /* Attach device memory and a stream.  Computes the line-solve coefficients
  * on the device (FP64 arithmetic) and uploads the launch tables.  May be called
- * again to move to other buffers or another stream.  stream may be NULL
+ * again to move to other buffers or another stream; the workspace is then
+ * re-initialised and cells must be uploaded again.  stream may be NULL
  * (the null stream; steps are then launched without a graph). */
 int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream);
 
@@ -158,6 +159,14 @@ int vl_sync(vl_ctx *ctx);
  * non-finite field values (status VL_E_NONFINITE when > 0). */
 int vl_mass(vl_ctx *ctx, int sim, double *out);
 int vl_check_finite(vl_ctx *ctx, long long *bad);
+
+/* Options.  VL_OPT_FUSE_SOURCES (FP32 path, default 1): 1 applies the cell
+ * sources inside the z sweep, right after each tile's stores (the occupied
+ * voxels of 64 z-lines form one contiguous range of a per-simulation list
+ * ordered by z-line); 0 applies them with a separate kernel over all occupied
+ * voxels.  Both give bitwise identical fields. */
+#define VL_OPT_FUSE_SOURCES 1
+int vl_set_option(vl_ctx *ctx, int option, int value);
 
 /* Per-kernel timing.  While enabled, vl_step launches without a graph and
  * brackets every kernel with HIP events on the bound stream.

@@ -25,6 +25,7 @@ VL_F32, VL_F64 = 0, 1
 VL_DECAY_ONCE, VL_DECAY_THIRDS = 0, 1
 VL_NEUMANN, VL_DIRICHLET = 0, 1
 VL_SOA, VL_AOS = 0, 1
+VL_OPT_FUSE_SOURCES = 1
 VL_K_SWEEP_X, VL_K_SWEEP_Y, VL_K_SWEEP_Z, VL_K_SOURCES, VL_K_DIRICHLET, VL_K_DECAY = range(6)
 KERNEL_NAMES = ["sweep_x", "sweep_y", "sweep_z", "sources", "dirichlet", "decay"]
 
@@ -51,6 +52,7 @@ SIGNATURES = {
     "vl_sync": (_i, [_vp]),
     "vl_mass": (_i, [_vp, _i, _dp]),
     "vl_check_finite": (_i, [_vp, C.POINTER(C.c_longlong)]),
+    "vl_set_option": (_i, [_vp, _i, _i]),
     "vl_set_profiling": (_i, [_vp, _i]),
     "vl_kernel_stats": (_i, [_vp, _i, C.POINTER(C.c_longlong), _dp]),
 }
@@ -203,6 +205,10 @@ def vl_check_finite(ctx) -> int:
     if rc not in (VL_OK, VL_E_NONFINITE):
         _check(rc, "vl_check_finite")
     return int(bad.value)
+
+
+def vl_set_option(ctx, option: int, value: int) -> None:
+    _check(lib().vl_set_option(ctx, int(option), int(value)), "vl_set_option")
 
 
 def vl_set_profiling(ctx, enable: bool) -> None:

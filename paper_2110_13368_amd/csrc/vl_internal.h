@@ -56,7 +56,18 @@ struct SimCells {
     int cell_base;   // first entry of the sorted per-cell arrays
     int comp_base;   // first float2 of the FP32 composites (n_occ x ns)
     int ab_base;     // first double2 of the sorted per-cell (a, b) (n_cells x ns)
-    int pad_;
+    int zl_base;     // first entry of the z-line starts (nx*ny + 1), -1 without cells
+};
+
+// Cell sources applied by the z sweep after its stores (FP32 path).  The
+// occupied voxels of a simulation are listed by z-line then k; line_start
+// gives each z-line's first entry.
+struct FusedSources {
+    const SimCells *cells;
+    const int *line_start;
+    const int *occ_vox;
+    const float2 *comp;
+    int enabled;
 };
 
 // ---------------------------------------------------------------------------
@@ -69,7 +80,7 @@ hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
                             const SubDev *subs, const float2 *coef, float *field,
-                            hipStream_t st);
+                            const FusedSources &src, hipStream_t st);
 
 // FP64 plain path: one thread per line, Thomas with the intermediate kept in
 // the field itself.  lines_prefix has nsubs+1 entries.
@@ -93,7 +104,10 @@ hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start,
                              int n_occ, int ns, const double *V, const double *S,
                              const double *U, const double *RS, double dt, double vvox,
-                             float2 *comp32, double2 *ab64, int n_in, hipStream_t st);
+                             const int *pos, float2 *comp32, double2 *ab64, hipStream_t st);
+hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
+                              unsigned long long *zkeys, int *occ_vox, int *pos, int *line_start,
+                              hipStream_t st);
 
 // a5/a6: sources over the occupied voxels of every simulation.
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix,

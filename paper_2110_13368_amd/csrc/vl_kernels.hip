@@ -382,6 +382,60 @@ hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id
     return hipGetLastError();
 }
 
+// FP32 path: occupied voxels re-ordered by z-line (i, j) then k, so that the
+// voxels of 64 consecutive z-lines form one contiguous range.  Keys are
+// ((line * nz + k) << 32) | (index in voxel order).
+__global__ void zline_keys_kernel(const int *__restrict__ occ_vox_v, int n_occ, int nxy, int nz,
+                                  unsigned long long *__restrict__ zkeys, int n_pad)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pad) return;
+    if (p >= n_occ) {
+        zkeys[p] = ~0ull;
+        return;
+    }
+    const int v = occ_vox_v[p];
+    const unsigned long long line = (unsigned)(v % nxy), k = (unsigned)(v / nxy);
+    zkeys[p] = ((line * (unsigned long long)nz + k) << 32) | (unsigned)p;
+}
+
+// After sorting the z keys: pos[voxel-order index] = z-order index, the
+// occupied voxel list in z order, and line_start[L] = first z-order entry of
+// z-line L (line_start[nxy] = n_occ).  Each entry fills the starts of the
+// lines between its predecessor's line and its own.
+__global__ void zline_scatter_kernel(const unsigned long long *__restrict__ zkeys, int n_occ, int nxy,
+                                     int nz, const int *__restrict__ occ_vox_v, int *__restrict__ occ_vox,
+                                     int *__restrict__ pos, int *__restrict__ line_start)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_occ) return;
+    const unsigned long long key = zkeys[p];
+    const int q = (int)(key & 0xffffffffull);
+    pos[q] = p;
+    occ_vox[p] = occ_vox_v[q];
+    const int L = (int)((key >> 32) / (unsigned long long)nz);
+    const int Lprev = (p == 0) ? -1 : (int)((zkeys[p - 1] >> 32) / (unsigned long long)nz);
+    for (int l = Lprev + 1; l <= L; ++l) line_start[l] = p;
+    if (p == n_occ - 1)
+        for (int l = L + 1; l <= nxy; ++l) line_start[l] = n_occ;
+}
+
+hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
+                              unsigned long long *zkeys, int *occ_vox, int *pos, int *line_start,
+                              hipStream_t st)
+{
+    if (n_occ <= 0) return hipSuccess;
+    int n_pad = 1;
+    while (n_pad < n_occ) n_pad <<= 1;
+    hipLaunchKernelGGL(zline_keys_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st, occ_vox_v, n_occ,
+                       nxy, nz, zkeys, n_pad);
+    hipError_t e = launch_bitonic_sort(zkeys, n_pad, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zline_scatter_kernel, dim3((n_occ + 255) / 256), dim3(256), 0, st, zkeys, n_occ,
+                       nxy, nz, occ_vox_v, occ_vox, pos, line_start);
+    return hipGetLastError();
+}
+
 // Per occupied voxel and substrate, walk its cells in upload order (FP64):
 //   a_i = k_i S_i rho*_i,  b_i = 1 + k_i (S_i + U_i),  k_i = dt V_i / V_vox,
 //   composite: A <- A + a_i B,  B <- B b_i  so that applying the cells one
@@ -391,12 +445,13 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
                                   const int *__restrict__ seg_start, int n_occ, int ns,
                                   const double *__restrict__ V, const double *__restrict__ S,
                                   const double *__restrict__ U, const double *__restrict__ RS,
-                                  double dt, double vvox, float2 *__restrict__ comp32,
-                                  double2 *__restrict__ ab64)
+                                  double dt, double vvox, const int *__restrict__ pos,
+                                  float2 *__restrict__ comp32, double2 *__restrict__ ab64)
 {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)n_occ * ns) return;
     const int seg = (int)(g / ns), s = (int)(g % ns);
+    const int out = pos ? pos[seg] : seg;
     double A = 0.0, B = 1.0;
     for (int p = seg_start[seg]; p < seg_start[seg + 1]; ++p) {
         const int i = (int)(keys[p] & 0xFFFFFFull);
@@ -408,19 +463,18 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
         A = A + a * B;
         B = B * b;
     }
-    if (comp32) comp32[(size_t)seg * ns + s] = make_float2((float)A, (float)(1.0 / B));
+    if (comp32) comp32[(size_t)out * ns + s] = make_float2((float)A, (float)(1.0 / B));
 }
 
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, int n_occ, int ns,
                              const double *V, const double *S, const double *U, const double *RS,
-                             double dt, double vvox, float2 *comp32, double2 *ab64, int n_in,
+                             double dt, double vvox, const int *pos, float2 *comp32, double2 *ab64,
                              hipStream_t st)
 {
-    (void)n_in;
     const long long total = (long long)n_occ * ns;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(composites_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys,
-                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, comp32, ab64);
+                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, ab64);
     return hipGetLastError();
 }
 

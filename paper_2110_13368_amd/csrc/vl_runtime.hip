@@ -54,7 +54,7 @@ struct SimHost {
     size_t vol_stride = 0;
     int sub0 = 0;
     // cell tables
-    int occ_base = 0, comp_base = 0, ab_base = 0;
+    int occ_base = 0, comp_base = 0, ab_base = 0, zl_base = -1;
     int n_cells = 0, n_occ = 0, n_out = 0;
     long long nvox() const { return (long long)n[0] * n[1] * n[2]; }
 };
@@ -98,12 +98,15 @@ struct vl_ctx {
     int stage_cells = 0;   // max over sims of max_cells
     int stage_ns = 0;      // max over sims of ns
     int key_pad = 0;       // next_pow2(stage_cells)
+    int zl_total = 0;      // sum over sims with cells of (nx*ny + 1)
+    bool fuse_sources = true;
 
     // workspace layout (byte offsets)
     size_t o_subs = 0, o_coef32 = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0;
     size_t o_cells = 0, o_occ_prefix = 0, o_occ_vox = 0, o_seg_start = 0, o_comp = 0, o_ab = 0;
     size_t o_pos = 0, o_V = 0, o_S = 0, o_U = 0, o_RS = 0, o_keys = 0, o_seg_id = 0;
     size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
+    size_t o_zkeys = 0, o_occ_tmp = 0, o_pos_idx = 0, o_line_start = 0;
     size_t n_coef32 = 0, n_coef64 = 0;
 
     char *ws = nullptr;
@@ -217,17 +220,20 @@ int enqueue_step(vl_ctx *ctx)
     if (ctx->precision == VL_F32) {
         float *field = (float *)ctx->field;
         const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+        const bool fused = ctx->fuse_sources && total_occ > 0;
+        const vl::FusedSources src{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
+                                   ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), fused ? 1 : 0};
         for (int axis = 0; axis < 3; ++axis)
             for (const Launch &L : ctx->launches) {
                 if (L.axis != axis) continue;
                 vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
                                   ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles};
                 rc = timed(ctx, VL_K_SWEEP_X + axis, [&] {
-                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, st);
+                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, src, st);
                 });
                 if (rc) return rc;
             }
-        if (total_occ > 0) {
+        if (total_occ > 0 && !fused) {
             rc = timed(ctx, VL_K_SOURCES, [&] {
                 return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
                                               ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
@@ -286,7 +292,7 @@ int upload_cell_tables(vl_ctx *ctx)
     std::vector<int> prefix(ctx->n_sims + 1, 0);
     for (int k = 0; k < ctx->n_sims; ++k) {
         const SimHost &s = ctx->sims[k];
-        cells[k] = vl::SimCells{s.sub0, s.ns, s.n_occ, s.occ_base, 0, s.comp_base, s.ab_base, 0};
+        cells[k] = vl::SimCells{s.sub0, s.ns, s.n_occ, s.occ_base, 0, s.comp_base, s.ab_base, s.zl_base};
         prefix[k + 1] = prefix[k] + s.n_occ;
     }
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_cells, cells.data(), cells.size() * sizeof(vl::SimCells),
@@ -556,10 +562,16 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->comp_total = 0;
     ctx->stage_cells = 0;
     ctx->stage_ns = 0;
+    ctx->zl_total = 0;
     for (SimHost &s : ctx->sims) {
         s.occ_base = ctx->cap_total;
         s.comp_base = ctx->comp_total;
         s.ab_base = ctx->comp_total;
+        s.zl_base = -1;
+        if (s.max_cells > 0 && ctx->precision == VL_F32) {
+            s.zl_base = ctx->zl_total;
+            ctx->zl_total += s.n[0] * s.n[1] + 1;
+        }
         ctx->cap_total += s.max_cells + 1;
         ctx->comp_total += s.max_cells * s.ns;
         ctx->stage_cells = std::max(ctx->stage_cells, s.max_cells);
@@ -597,6 +609,11 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_mass_part = take(sizeof(double) * vl::kMassBlocks);
     ctx->o_mass_out = take(sizeof(double) * ctx->max_ns);
     ctx->o_count = take(sizeof(unsigned long long));
+    const bool zorder = ctx->precision == VL_F32;
+    ctx->o_zkeys = take(zorder ? sizeof(unsigned long long) * ctx->key_pad : 0);
+    ctx->o_occ_tmp = take(zorder ? sizeof(int) * (ctx->stage_cells + 1) : 0);
+    ctx->o_pos_idx = take(zorder ? sizeof(int) * ctx->stage_cells : 0);
+    ctx->o_line_start = take(sizeof(int) * ctx->zl_total);
     ctx->ws_bytes = w;
 
     ctx->finalized = true;
@@ -631,6 +648,13 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
                                    ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
                                    ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
                                    ctx->at<SubDev>(ctx->o_subs), st));
+    if (ctx->zl_total > 0)
+        VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_line_start, 0, sizeof(int) * ctx->zl_total, st));
+    for (SimHost &s : ctx->sims) {
+        s.n_cells = 0;
+        s.n_occ = 0;
+        s.n_out = 0;
+    }
     ctx->bound = true;
     if (int rc = upload_cell_tables(ctx)) return rc;
     VL_HIP(hipStreamSynchronize(st));
@@ -736,6 +760,9 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
     s.n_cells = n;
     s.n_occ = 0;
     s.n_out = 0;
+    if (s.zl_base >= 0)
+        VL_HIP(hipMemsetAsync(ctx->at<int>(ctx->o_line_start) + s.zl_base, 0,
+                              sizeof(int) * ((size_t)s.n[0] * s.n[1] + 1), st));
     if (n == 0) {
         if (n_out_of_domain) *n_out_of_domain = 0;
         return upload_cell_tables(ctx);
@@ -759,18 +786,29 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
     const int n_in = n - n_out;
     int n_occ = 0;
     if (n_in > 0) {
-        VL_HIP(vl::launch_segments(keys, n_in, ctx->at<int>(ctx->o_seg_id), ctx->at<int>(ctx->o_occ_vox) + s.occ_base,
+        // FP32: occupied voxels first in voxel order (temporary), then
+        // re-ordered by z-line for the sources fused into the z sweep.
+        const bool zorder = ctx->precision == VL_F32;
+        int *occ_v = zorder ? ctx->at<int>(ctx->o_occ_tmp) : ctx->at<int>(ctx->o_occ_vox) + s.occ_base;
+        VL_HIP(vl::launch_segments(keys, n_in, ctx->at<int>(ctx->o_seg_id), occ_v,
                                    ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters + 1, st));
         VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
         VL_HIP(hipStreamSynchronize(st));
         n_occ = host_counters[1];
+        int *pos = nullptr;
+        if (zorder) {
+            pos = ctx->at<int>(ctx->o_pos_idx);
+            VL_HIP(vl::launch_zline_order(occ_v, n_occ, s.n[0] * s.n[1], s.n[2],
+                                          ctx->at<unsigned long long>(ctx->o_zkeys),
+                                          ctx->at<int>(ctx->o_occ_vox) + s.occ_base, pos,
+                                          ctx->at<int>(ctx->o_line_start) + s.zl_base, st));
+        }
         const double vvox = s.h[0] * s.h[1] * s.h[2];
         VL_HIP(vl::launch_composites(keys, ctx->at<int>(ctx->o_seg_start) + s.occ_base, n_occ, s.ns,
                                      ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S),
                                      ctx->at<double>(ctx->o_U), ctx->at<double>(ctx->o_RS), ctx->dt, vvox,
-                                     ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
-                                     ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_ab) + s.ab_base : nullptr,
-                                     n_in, st));
+                                     pos, zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
+                                     zorder ? nullptr : ctx->at<double2>(ctx->o_ab) + s.ab_base, st));
     }
     s.n_occ = n_occ;
     s.n_out = n_out;
@@ -846,6 +884,18 @@ int vl_check_finite(vl_ctx *ctx, long long *bad)
     if (bad) *bad = (long long)h;
     if (h > 0) return fail(VL_E_NONFINITE, std::to_string(h) + " non-finite field values");
     return VL_OK;
+}
+
+int vl_set_option(vl_ctx *ctx, int option, int value)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (option == VL_OPT_FUSE_SOURCES) {
+        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_FUSE_SOURCES takes 0 or 1");
+        if (ctx->fuse_sources != (value == 1)) drop_graph(ctx);
+        ctx->fuse_sources = value == 1;
+        return VL_OK;
+    }
+    return fail(VL_E_ARG, "unknown option");
 }
 
 int vl_set_profiling(vl_ctx *ctx, int enable)

@@ -145,7 +145,7 @@ __host__ __device__ constexpr int waves_for_cap(int cap)
 template <int AXIS, int CAP>
 __global__ void __launch_bounds__(128)
 sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
-          float *__restrict__ field)
+          float *__restrict__ field, FusedSources src)
 {
     constexpr int kChunks = (CAP + 63) / 64;
     constexpr int kStage = (AXIS == 0) ? 2 * 64 * 65 : 1;
@@ -360,34 +360,60 @@ sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restri
         const int row0 = top ? 0 : (n - 1) * row_b;
         const int step = top ? row_b : -row_b;
         VL_FOR_UP(CAP, nel, t, bstore(rs, lane_b, row0 + t * step, v[t]);)
+
+        // ---- cell sources of this tile's z-lines (after the last P_D) ----
+        if (AXIS == 2 && src.enabled) {
+            const SimCells &C = src.cells[S.sim];
+            if (C.zl_base >= 0) {
+                const int nlines = nx * ny;
+                const int L0 = local * kTileLines;
+                const int *ls = src.line_start + C.zl_base;
+                const int e0 = ls[L0], e1 = ls[min(L0 + kTileLines, nlines)];
+                if (e1 > e0) {
+                    // both waves' stores of this tile complete and visible
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    const __amdgpu_buffer_rsrc_t rv = make_rsrc(field + S.base, S.vol);
+                    for (int e = e0 + (int)threadIdx.x; e < e1; e += 128) {
+                        const int vox = src.occ_vox[C.occ_base + e];
+                        const float2 ab = src.comp[C.comp_base + (size_t)e * C.ns + S.sub];
+                        const unsigned off = (unsigned)vox * 4u;
+                        const float r = bload(rv, off, 0);
+                        bstore(rv, off, 0, (r + ab.x) * ab.y);
+                    }
+                }
+            }
+        }
     }
 }
 
 template <int AXIS>
 static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *subs,
-                              const float2 *coef, float *field, hipStream_t st)
+                              const float2 *coef, float *field, const FusedSources &src,
+                              hipStream_t st)
 {
     const dim3 grid(L.total_tiles), block(128);
     switch (cap_idx) {
-    case 0: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[0]>), grid, block, 0, st, L, subs, coef, field); break;
-    case 1: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[1]>), grid, block, 0, st, L, subs, coef, field); break;
-    case 2: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[2]>), grid, block, 0, st, L, subs, coef, field); break;
-    case 3: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[3]>), grid, block, 0, st, L, subs, coef, field); break;
-    case 4: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, field); break;
-    case 5: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, field); break;
-    case 6: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, field); break;
+    case 0: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[0]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 1: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[1]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 2: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[2]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 3: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[3]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 4: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 5: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 6: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, field, src); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,
-                            const float2 *coef, float *field, hipStream_t st)
+                            const float2 *coef, float *field, const FusedSources &src,
+                            hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;
-    if (axis == 0) return launch_axis<0>(cap_idx, L, subs, coef, field, st);
-    if (axis == 1) return launch_axis<1>(cap_idx, L, subs, coef, field, st);
-    if (axis == 2) return launch_axis<2>(cap_idx, L, subs, coef, field, st);
+    if (axis == 0) return launch_axis<0>(cap_idx, L, subs, coef, field, src, st);
+    if (axis == 1) return launch_axis<1>(cap_idx, L, subs, coef, field, src, st);
+    if (axis == 2) return launch_axis<2>(cap_idx, L, subs, coef, field, src, st);
     return hipErrorInvalidValue;
 }
 

@@ -137,6 +137,19 @@ def test_bitwise_repeatable_and_graph_equals_direct():
     assert np.array_equal(a, c)
 
 
+def test_fused_sources_equal_standalone_kernel():
+    """Sources applied inside the z sweep and by the separate kernel give the
+    same bits (same FP32 arithmetic, each voxel touched once)."""
+    wl = W.batched(n_sims=4, edge_range=(9, 90), cells_range=(200, 3000))
+    spec = _spec((61, 47, 83), 3, "mixed", 4000, "f32", 51, layout="gaussian")
+    for specs in (wl.sims, [spec]):
+        fused, _ = run_gpu(specs, 12)
+        alone, _ = run_gpu(specs, 12, fuse=False)
+        for a, b in zip(fused, alone):
+            assert np.array_equal(a, b)
+    assert_close(fused[0], run_oracle(spec, 12), 1e-5, "fused sources")
+
+
 def test_batch_of_one_equals_single():
     wl = W.batched(n_sims=3, edge_range=(10, 40), cells_range=(50, 200))
     fields, _ = run_gpu(wl.sims, 7)
