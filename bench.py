@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-reference", action="store_true")
+    ap.add_argument("--mode", default="tuned", choices=["tuned", "launches", "persistent"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -136,6 +137,14 @@ def main():
 
     precision = vb.VL_F64 if wl.dtype == "f64" else vb.VL_F32
     ctx = vb.Context(wl.sims, precision=precision)
+    if args.mode == "tuned":
+        ctx.tune(None)  # times the step modes on these buffers; setup, not timed
+    else:
+        ctx.set_option(vb.VL_OPT_STEP_MODE,
+                       vb.VL_MODE_PERSISTENT if args.mode == "persistent" else vb.VL_MODE_LAUNCHES)
+    mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
+    for k, s in enumerate(wl.sims):
+        ctx.set_field(k, s.rho0)
     elapsed = time_steps(ctx, args.steps, args.warmup)
     value = E * args.steps / elapsed
     esize = 8 if precision == vb.VL_F64 else 4
@@ -153,6 +162,8 @@ def main():
     launches_per_step = launches / args.steps
     if dom.startswith("sweep"):
         alg_bytes = 2 * esize * E  # every element read once and written once per sweep
+    elif dom == "step":
+        alg_bytes = b_alg * E  # the one-launch step: three sweeps
     else:
         alg_bytes = None
     roofline = {
@@ -199,7 +210,7 @@ def main():
         "config": {"workload": wl.name, "sims": len(wl.sims), "voxel_substrates": E,
                    "grid": list(wl.sims[0].shape) if len(wl.sims) == 1 else "ragged",
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
-                   "dt": wl.sims[0].dt, "parallelism": "single-gpu"},
+                   "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode},
         "hbm_effective": {"bytes_per_update": b_alg,
                           "GBps": round(b_alg * value / 1e9, 1),
                           "frac_of_peak": round(b_alg * value / 1e9 / HBM_PEAK_GBS, 4)},

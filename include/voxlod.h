@@ -90,7 +90,8 @@ extern "C" {
 #define VL_K_SOURCES 3
 #define VL_K_DIRICHLET 4
 #define VL_K_DECAY 5
-#define VL_K_COUNT 6
+#define VL_K_STEP 6 /* the one-launch step (VL_MODE_PERSISTENT) */
+#define VL_K_COUNT 7
 
 typedef struct vl_ctx vl_ctx;
 
@@ -166,7 +167,37 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * ordered by z-line); 0 applies them with a separate kernel over all occupied
  * voxels.  Both give bitwise identical fields. */
 #define VL_OPT_FUSE_SOURCES 1
+/* VL_OPT_STEP_MODE (FP32 path): VL_MODE_LAUNCHES (default) launches one
+ * kernel per sweep and capacity class, each covering every simulation;
+ * VL_MODE_PERSISTENT runs the whole step as one launch whose workgroups take
+ * tiles from a single queue (all x tiles, then y, then z) and start a volume's
+ * y (z) tiles once its x (y) tiles are done, so ragged batches need no global
+ * barrier.  VL_OPT_PERSISTENT_GRID: workgroups of that launch (0 = as many
+ * as fit on the device at once).  VL_OPT_WAIT_LIMIT_US: microseconds a tile
+ * may wait for the previous sweep of its volume before it gives up (default
+ * 2000000); giving up makes the next vl_sync fail with VL_E_STATE, so a step
+ * can never hang (the limit exists for tests of that path). */
+#define VL_OPT_STEP_MODE 2
+#define VL_OPT_PERSISTENT_GRID 3
+#define VL_OPT_WAIT_LIMIT_US 4
+#define VL_MODE_LAUNCHES 0
+#define VL_MODE_PERSISTENT 1
+/* VL_OPT_XCD_ORDER (default 1): workgroup b of a sweep runs on XCD b mod 8;
+ * with 1 each XCD gets a contiguous range of tiles (neighbouring tiles share
+ * an L2), with 0 tiles follow the workgroup index. */
+#define VL_OPT_XCD_ORDER 5
+/* Selecting VL_MODE_PERSISTENT currently fails with VL_E_STATE: the one-launch
+ * step is switched off until a hang seen in its first GPU runs is explained. */
 int vl_set_option(vl_ctx *ctx, int option, int value);
+int vl_get_option(vl_ctx *ctx, int option, int *value);
+
+/* Autotuner: times the candidate launch configurations (XCD tile order on or
+ * off, sources fused into the z sweep or separate) on the bound buffers, a
+ * few steps each (which overwrite the field), and keeps the fastest.  With a
+ * non-NULL cache_path the choice is read from / appended to that text file,
+ * keyed by precision, decay split and every volume's shape, so a second call
+ * for the same shapes does no timing.  No-op for VL_F64. */
+int vl_tune(vl_ctx *ctx, const char *cache_path);
 
 /* Per-kernel timing.  While enabled, vl_step launches without a graph and
  * brackets every kernel with HIP events on the bound stream.

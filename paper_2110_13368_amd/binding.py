@@ -25,9 +25,11 @@ VL_F32, VL_F64 = 0, 1
 VL_DECAY_ONCE, VL_DECAY_THIRDS = 0, 1
 VL_NEUMANN, VL_DIRICHLET = 0, 1
 VL_SOA, VL_AOS = 0, 1
-VL_OPT_FUSE_SOURCES = 1
-VL_K_SWEEP_X, VL_K_SWEEP_Y, VL_K_SWEEP_Z, VL_K_SOURCES, VL_K_DIRICHLET, VL_K_DECAY = range(6)
-KERNEL_NAMES = ["sweep_x", "sweep_y", "sweep_z", "sources", "dirichlet", "decay"]
+VL_OPT_FUSE_SOURCES, VL_OPT_STEP_MODE, VL_OPT_PERSISTENT_GRID, VL_OPT_WAIT_LIMIT_US = 1, 2, 3, 4
+VL_MODE_LAUNCHES, VL_MODE_PERSISTENT = 0, 1
+VL_OPT_XCD_ORDER = 5
+VL_K_SWEEP_X, VL_K_SWEEP_Y, VL_K_SWEEP_Z, VL_K_SOURCES, VL_K_DIRICHLET, VL_K_DECAY, VL_K_STEP = range(7)
+KERNEL_NAMES = ["sweep_x", "sweep_y", "sweep_z", "sources", "dirichlet", "decay", "step"]
 
 # exported symbol -> (restype, argtypes)
 _vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
@@ -53,6 +55,8 @@ SIGNATURES = {
     "vl_mass": (_i, [_vp, _i, _dp]),
     "vl_check_finite": (_i, [_vp, C.POINTER(C.c_longlong)]),
     "vl_set_option": (_i, [_vp, _i, _i]),
+    "vl_get_option": (_i, [_vp, _i, _ip]),
+    "vl_tune": (_i, [_vp, C.c_char_p]),
     "vl_set_profiling": (_i, [_vp, _i]),
     "vl_kernel_stats": (_i, [_vp, _i, C.POINTER(C.c_longlong), _dp]),
 }
@@ -211,6 +215,16 @@ def vl_set_option(ctx, option: int, value: int) -> None:
     _check(lib().vl_set_option(ctx, int(option), int(value)), "vl_set_option")
 
 
+def vl_get_option(ctx, option: int) -> int:
+    v = C.c_int(0)
+    _check(lib().vl_get_option(ctx, int(option), C.byref(v)), "vl_get_option")
+    return int(v.value)
+
+
+def vl_tune(ctx, cache_path: Optional[str] = None) -> None:
+    _check(lib().vl_tune(ctx, cache_path.encode() if cache_path else None), "vl_tune")
+
+
 def vl_set_profiling(ctx, enable: bool) -> None:
     _check(lib().vl_set_profiling(ctx, int(bool(enable))), "vl_set_profiling")
 
@@ -321,6 +335,16 @@ class Context:
 
     def check_finite(self) -> int:
         return vl_check_finite(self.h)
+
+    def set_option(self, option: int, value: int) -> None:
+        vl_set_option(self.h, option, value)
+
+    def get_option(self, option: int) -> int:
+        return vl_get_option(self.h, option)
+
+    def tune(self, cache_path: Optional[str] = None) -> None:
+        """Pick the step mode and launch size by timing (overwrites the field)."""
+        vl_tune(self.h, cache_path)
 
     def set_profiling(self, on: bool) -> None:
         vl_set_profiling(self.h, on)

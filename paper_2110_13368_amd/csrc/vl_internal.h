@@ -45,6 +45,7 @@ struct SweepLaunch {
     const int *tile_prefix;  // count+1 exclusive prefix of their tile counts
     int count;
     int total_tiles;
+    int xcd_order;           // 1: give each XCD a contiguous range of tiles
 };
 
 // Per-simulation cell tables (all offsets in elements of their arrays).
@@ -70,6 +71,18 @@ struct FusedSources {
     int enabled;
 };
 
+// One launch for a whole step: tiles of all three sweeps in one queue.
+struct StepQueue {
+    const int *sub_ids;     // volumes (count)
+    const int *prefix;      // 3 x (count + 1) exclusive tile prefixes, one row per axis
+    int count;
+    int phase_start[4];     // first queue index of the x, y, z tiles; [3] = total
+    unsigned *counters;     // [0] queue head, [1] workgroups done, [2..] done tiles per (axis, volume)
+    int *error;             // set to 1 when a wait gives up
+    unsigned long long wait_ticks;  // wall-clock ticks a wait may take before giving up
+    unsigned zero;          // always 0: the operand of the atomic reads of the counters
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files, called by the runtime).
 
@@ -81,6 +94,12 @@ hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
                             const SubDev *subs, const float2 *coef, float *field,
                             const FusedSources &src, hipStream_t st);
+
+// a8: the whole step as one persistent launch of `grid` workgroups.
+hipError_t launch_step_persistent(int cap_idx, int grid, const StepQueue &Q, const SubDev *subs,
+                                  const float2 *coef, float *field, const FusedSources &src,
+                                  hipStream_t st);
+hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks);
 
 // FP64 plain path: one thread per line, Thomas with the intermediate kept in
 // the field itself.  lines_prefix has nsubs+1 entries.

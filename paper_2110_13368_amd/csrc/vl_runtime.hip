@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -100,6 +101,17 @@ struct vl_ctx {
     int key_pad = 0;       // next_pow2(stage_cells)
     int zl_total = 0;      // sum over sims with cells of (nx*ny + 1)
     bool fuse_sources = true;
+    bool xcd_order = true;
+
+    // one-launch step (FP32): queue over all tiles of the three sweeps
+    int step_mode = VL_MODE_LAUNCHES;
+    int persistent_grid = 0;      // workgroups; 0 = all that fit at once
+    int queue_cap_idx = 0;
+    int queue_total = 0;
+    int queue_phase[4] = {0, 0, 0, 0};
+    size_t q_ids_off = 0, q_prefix_off = 0;  // offsets into itable
+    size_t o_qcounters = 0, o_qerror = 0;
+    int wait_limit_us = 2000000;  // a tile of the one-launch step waits at most this long
 
     // workspace layout (byte offsets)
     size_t o_subs = 0, o_coef32 = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0;
@@ -150,6 +162,11 @@ void drop_graph(vl_ctx *ctx)
     ctx->graph = nullptr;
     ctx->graph_valid = false;
 }
+
+// The one-launch step (VL_MODE_PERSISTENT) did not finish in its first two
+// GPU runs (the second with every wait bounded in time), and the cause is not
+// yet shown; until it is, selecting it is refused.
+bool one_launch_enabled() { return false; }
 
 int cap_index(int cb)
 {
@@ -223,16 +240,41 @@ int enqueue_step(vl_ctx *ctx)
         const bool fused = ctx->fuse_sources && total_occ > 0;
         const vl::FusedSources src{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
                                    ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), fused ? 1 : 0};
+        if (ctx->step_mode == VL_MODE_PERSISTENT) {
+            const int *it = ctx->at<int>(ctx->o_itable);
+            int dev = 0, khz = 100000;
+            VL_HIP(hipGetDevice(&dev));
+            VL_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            const unsigned long long ticks =
+                (unsigned long long)ctx->wait_limit_us * (unsigned long long)std::max(khz, 1) / 1000ull;
+            vl::StepQueue Q{it + ctx->q_ids_off, it + ctx->q_prefix_off, nsubs,
+                            {ctx->queue_phase[0], ctx->queue_phase[1], ctx->queue_phase[2], ctx->queue_phase[3]},
+                            ctx->at<unsigned>(ctx->o_qcounters), ctx->at<int>(ctx->o_qerror), ticks, 0u};
+            int grid = ctx->persistent_grid;
+            if (grid <= 0) {
+                int per_cu = 1, cus = 1;
+                VL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                VL_HIP(vl::persistent_blocks_per_cu(ctx->queue_cap_idx, &per_cu));
+                grid = std::max(1, per_cu) * cus;
+            }
+            grid = std::min(grid, ctx->queue_total);
+            rc = timed(ctx, VL_K_STEP, [&] {
+                return vl::launch_step_persistent(ctx->queue_cap_idx, grid, Q, subs, coef, field, src, st);
+            });
+            if (rc) return rc;
+        } else {
         for (int axis = 0; axis < 3; ++axis)
             for (const Launch &L : ctx->launches) {
                 if (L.axis != axis) continue;
                 vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
-                                  ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles};
+                                  ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
+                                  ctx->xcd_order ? 1 : 0};
                 rc = timed(ctx, VL_K_SWEEP_X + axis, [&] {
                     return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, src, st);
                 });
                 if (rc) return rc;
             }
+        }
         if (total_occ > 0 && !fused) {
             rc = timed(ctx, VL_K_SOURCES, [&] {
                 return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
@@ -513,6 +555,30 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             }
         }
     }
+    // one-launch step: every volume, tiles of x, then y, then z in one queue
+    ctx->queue_cap_idx = 0;
+    ctx->queue_total = 0;
+    if (ctx->precision == VL_F32) {
+        ctx->q_ids_off = ctx->itable.size();
+        for (int q = 0; q < nsubs; ++q) ctx->itable.push_back(q);
+        ctx->q_prefix_off = ctx->itable.size();
+        ctx->queue_phase[0] = 0;
+        for (int axis = 0; axis < 3; ++axis) {
+            long long acc = 0;
+            for (int q = 0; q < nsubs; ++q) {
+                const SubDev &d = ctx->subs[q];
+                ctx->itable.push_back((int)acc);
+                acc += (d.vol / d.n[axis] + vl::kTileLines - 1) / vl::kTileLines;
+                ctx->queue_cap_idx =
+                    std::max(ctx->queue_cap_idx, cap_index(d.n[axis] - 1 - (d.n[axis] - 1) / 2));
+            }
+            ctx->itable.push_back((int)acc);
+            if ((long long)ctx->queue_phase[axis] + acc >= (1ll << 31))
+                return fail(VL_E_SHAPE, "too many tiles for one step queue");
+            ctx->queue_phase[axis + 1] = ctx->queue_phase[axis] + (int)acc;
+        }
+        ctx->queue_total = ctx->queue_phase[3];
+    }
     if (ctx->itable.empty()) ctx->itable.push_back(0);
 
     // FP64 plain tables: line prefixes per axis, voxel prefix, Dirichlet faces
@@ -614,6 +680,8 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_occ_tmp = take(zorder ? sizeof(int) * (ctx->stage_cells + 1) : 0);
     ctx->o_pos_idx = take(zorder ? sizeof(int) * ctx->stage_cells : 0);
     ctx->o_line_start = take(sizeof(int) * ctx->zl_total);
+    ctx->o_qcounters = take(sizeof(unsigned) * (2 + 3 * (size_t)nsubs));
+    ctx->o_qerror = take(sizeof(int));
     ctx->ws_bytes = w;
 
     ctx->finalized = true;
@@ -650,6 +718,8 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
                                    ctx->at<SubDev>(ctx->o_subs), st));
     if (ctx->zl_total > 0)
         VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_line_start, 0, sizeof(int) * ctx->zl_total, st));
+    VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_qcounters, 0, sizeof(unsigned) * (2 + 3 * ctx->subs.size()), st));
+    VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_qerror, 0, sizeof(int), st));
     for (SimHost &s : ctx->sims) {
         s.n_cells = 0;
         s.n_occ = 0;
@@ -851,6 +921,15 @@ int vl_sync(vl_ctx *ctx)
 {
     if (int rc = check_ctx(ctx)) return rc;
     VL_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->bound) {
+        int err = 0;
+        VL_HIP(hipMemcpy(&err, ctx->ws + ctx->o_qerror, sizeof err, hipMemcpyDeviceToHost));
+        if (err) {
+            VL_HIP(hipMemset(ctx->ws + ctx->o_qerror, 0, sizeof err));
+            return fail(VL_E_STATE, "one-launch step: a tile gave up waiting for the previous sweep "
+                                    "(wait limit reached); the field is not valid");
+        }
+    }
     return VL_OK;
 }
 
@@ -895,7 +974,161 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         ctx->fuse_sources = value == 1;
         return VL_OK;
     }
+    if (option == VL_OPT_STEP_MODE) {
+        if (value != VL_MODE_LAUNCHES && value != VL_MODE_PERSISTENT)
+            return fail(VL_E_ARG, "VL_OPT_STEP_MODE takes VL_MODE_LAUNCHES or VL_MODE_PERSISTENT");
+        if (value == VL_MODE_PERSISTENT && ctx->precision != VL_F32)
+            return fail(VL_E_ARG, "the one-launch step exists for the FP32 path only");
+        if (value == VL_MODE_PERSISTENT && !one_launch_enabled())
+            return fail(VL_E_STATE, "the one-launch step is switched off: its first GPU runs did not "
+                                    "finish and the cause is not yet known");
+        if (ctx->step_mode != value) drop_graph(ctx);
+        ctx->step_mode = value;
+        return VL_OK;
+    }
+    if (option == VL_OPT_PERSISTENT_GRID) {
+        if (value < 0) return fail(VL_E_ARG, "VL_OPT_PERSISTENT_GRID must be >= 0");
+        if (ctx->persistent_grid != value) drop_graph(ctx);
+        ctx->persistent_grid = value;
+        return VL_OK;
+    }
+    if (option == VL_OPT_XCD_ORDER) {
+        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_XCD_ORDER takes 0 or 1");
+        if (ctx->xcd_order != (value == 1)) drop_graph(ctx);
+        ctx->xcd_order = value == 1;
+        return VL_OK;
+    }
+    if (option == VL_OPT_WAIT_LIMIT_US) {
+        if (value < 0) return fail(VL_E_ARG, "VL_OPT_WAIT_LIMIT_US must be >= 0");
+        if (ctx->wait_limit_us != value) drop_graph(ctx);
+        ctx->wait_limit_us = value;
+        return VL_OK;
+    }
     return fail(VL_E_ARG, "unknown option");
+}
+
+int vl_get_option(vl_ctx *ctx, int option, int *value)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!value) return fail(VL_E_ARG, "value is null");
+    switch (option) {
+    case VL_OPT_FUSE_SOURCES: *value = ctx->fuse_sources ? 1 : 0; return VL_OK;
+    case VL_OPT_STEP_MODE: *value = ctx->step_mode; return VL_OK;
+    case VL_OPT_PERSISTENT_GRID: *value = ctx->persistent_grid; return VL_OK;
+    case VL_OPT_WAIT_LIMIT_US: *value = ctx->wait_limit_us; return VL_OK;
+    case VL_OPT_XCD_ORDER: *value = ctx->xcd_order ? 1 : 0; return VL_OK;
+    default: return fail(VL_E_ARG, "unknown option");
+    }
+}
+
+// Key of the tuning cache: everything the launch shapes depend on.
+static std::string tune_key(const vl_ctx *ctx)
+{
+    std::string k = "p" + std::to_string(ctx->precision) + "d" + std::to_string(ctx->decay);
+    unsigned long long h = 1469598103934665603ull;  // FNV-1a over the volume shapes
+    auto mix = [&](long long x) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (unsigned long long)((x >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const SimHost &s : ctx->sims) {
+        mix(s.n[0]);
+        mix(s.n[1]);
+        mix(s.n[2]);
+        mix(s.ns);
+        mix(s.max_cells > 0);
+    }
+    char buf[32];
+    std::snprintf(buf, sizeof buf, "%016llx", h);
+    return k + "s" + std::to_string(ctx->n_sims) + "h" + buf;
+}
+
+int vl_tune(vl_ctx *ctx, const char *cache_path)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    if (ctx->precision != VL_F32) return VL_OK;  // the plain path has one shape
+    const std::string key = tune_key(ctx);
+    // a candidate: step mode, its grid, XCD-ordered tiles, fused sources
+    struct Cand {
+        int mode, grid, xcd, fuse;
+    };
+    auto apply = [&](const Cand &c) -> int {
+        if (int rc = vl_set_option(ctx, VL_OPT_STEP_MODE, c.mode)) return rc;
+        if (int rc = vl_set_option(ctx, VL_OPT_PERSISTENT_GRID, c.grid)) return rc;
+        if (int rc = vl_set_option(ctx, VL_OPT_XCD_ORDER, c.xcd)) return rc;
+        return vl_set_option(ctx, VL_OPT_FUSE_SOURCES, c.fuse);
+    };
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char k[128];
+            Cand c{0, 0, 1, 1};
+            bool hit = false;
+            while (std::fscanf(f, "%127s %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse) == 5)
+                if (key == k) {
+                    hit = true;
+                    break;
+                }
+            std::fclose(f);
+            if (hit && (c.mode != VL_MODE_PERSISTENT || one_launch_enabled())) return apply(c);
+        }
+    }
+    std::vector<Cand> cands;
+    for (int xcd = 1; xcd >= 0; --xcd)
+        for (int fuse = 1; fuse >= 0; --fuse) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse});
+    if (one_launch_enabled()) {
+        int per_cu = 1, cus = 1, dev = 0;
+        VL_HIP(hipGetDevice(&dev));
+        VL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        VL_HIP(vl::persistent_blocks_per_cu(ctx->queue_cap_idx, &per_cu));
+        per_cu = std::max(per_cu, 1);
+        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1});
+    }
+    const bool was_profiling = ctx->profiling;
+    ctx->profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VL_HIP(hipEventCreate(&e0));
+    VL_HIP(hipEventCreate(&e1));
+    float best = 0.f;
+    Cand pick = cands[0];
+    int rc = VL_OK;
+    for (const Cand &c : cands) {
+        if ((rc = apply(c))) break;
+        if ((rc = vl_step(ctx, 2))) break;
+        float ms = 0.f;
+        int steps = 3;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = fail(VL_E_HIP, "hipEventRecord failed");
+            if (!rc) rc = vl_step(ctx, steps);
+            if (!rc && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = fail(VL_E_HIP, "hipEventRecord failed");
+            if (!rc) rc = vl_sync(ctx);
+            if (rc) break;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(VL_E_HIP, "hipEventElapsedTime failed");
+                break;
+            }
+            ms /= steps;
+            steps = std::max(3, std::min(100, (int)(40.f / std::max(ms, 1e-3f))));
+        }
+        if (rc) break;
+        if (best == 0.f || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profiling = was_profiling;
+    if (rc) return rc;
+    if ((rc = apply(pick))) return rc;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse);
+            std::fclose(f);
+        }
+    }
+    return VL_OK;
 }
 
 int vl_set_profiling(vl_ctx *ctx, int enable)

@@ -142,21 +142,27 @@ __host__ __device__ constexpr int waves_for_cap(int cap)
     return cap <= 64 ? 4 : cap <= 128 ? 3 : cap <= 200 ? 2 : 1;
 }
 
-template <int AXIS, int CAP>
-__global__ void __launch_bounds__(128)
-sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
-          float *__restrict__ field, FusedSources src)
+// LDS of one tile.  The x sweep needs the 64x65 staging block per wave; the
+// others only the exchange slots and the pivot table.
+template <int CAP, bool XSTAGE>
+struct TileLds {
+    float xch[2][kWave];
+    float2 piv[CAP];
+    float stage[XSTAGE ? 2 * 64 * 65 : 1];
+};
+
+// One tile of one sweep: 64 lines of volume S, tile index `local` within the
+// volume's tiles of this axis.  Called by every thread of a 128-thread
+// workgroup (it contains workgroup barriers).
+template <int AXIS, int CAP, bool XSTAGE>
+__device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const float2 *__restrict__ coef,
+                                           float *__restrict__ field, const FusedSources &src,
+                                           TileLds<CAP, XSTAGE> &sh)
 {
     constexpr int kChunks = (CAP + 63) / 64;
-    constexpr int kStage = (AXIS == 0) ? 2 * 64 * 65 : 1;
-    __shared__ float xch[2][kWave];
-    __shared__ float2 cs_lds[CAP];
-    __shared__ float stage[kStage];
-
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int slot = find_slot(L.tile_prefix, L.count, tile);
-    const int local = tile - L.tile_prefix[slot];
-    const SubDev &S = subs[L.sub_ids[slot]];
+    float(&xch)[2][kWave] = sh.xch;
+    float2 *cs_lds = sh.piv;
+    float *stage = sh.stage;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -387,6 +393,96 @@ sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restri
     }
 }
 
+template <int AXIS, int CAP>
+__global__ void __launch_bounds__(128)
+sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
+          float *__restrict__ field, FusedSources src)
+{
+    __shared__ TileLds<CAP, AXIS == 0> sh;
+    const int tile = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int slot = find_slot(L.tile_prefix, L.count, tile);
+    const int local = tile - L.tile_prefix[slot];
+    sweep_tile<AXIS, CAP, AXIS == 0>(subs[L.sub_ids[slot]], local, coef, field, src, sh);
+}
+
+// The whole step in one launch.  Workgroups take tiles from one queue in the
+// order: every x tile, then every y tile, then every z tile (volume by
+// volume).  A y (z) tile of a volume first waits until all x (y) tiles of
+// that volume are done.  Those tiles were taken earlier by workgroups that
+// are running and never wait on later tiles, so the waits always end,
+// whatever the grid size.  A wait that exceeds spin_limit sets *error and
+// gives up (the step is then wrong, but every wave exits).  The last
+// workgroup to leave resets the counters for the next launch.
+template <int CAP>
+__global__ void __launch_bounds__(128)
+sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
+                      float *__restrict__ field, FusedSources src)
+{
+    __shared__ TileLds<CAP, true> sh;
+    __shared__ int s_tile;
+    unsigned *head = Q.counters;
+    unsigned *exited = Q.counters + 1;
+    unsigned *done = Q.counters + 2;  // [phase][slot]
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= Q.phase_start[3]) break;
+        const int phase = t < Q.phase_start[1] ? 0 : (t < Q.phase_start[2] ? 1 : 2);
+        const int tp = t - Q.phase_start[phase];
+        const int *prefix = Q.prefix + phase * (Q.count + 1);
+        const int slot = find_slot(prefix, Q.count, tp);
+        const int local = tp - prefix[slot];
+        if (phase > 0) {
+            if (threadIdx.x == 0) {
+                const int *pp = Q.prefix + (phase - 1) * (Q.count + 1);
+                const unsigned need = (unsigned)(pp[slot + 1] - pp[slot]);
+                unsigned *d = done + (phase - 1) * Q.count + slot;
+                // The counter is read with an atomic read-modify-write: each
+                // XCD has its own L2, and a plain load may keep returning a
+                // stale line of it; RMW atomics act at the coherence point.
+                // Q.zero (0, but not a constant here) keeps the compiler from
+                // turning the idempotent add into a load.
+                if (__hip_atomic_fetch_add(d, Q.zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    const unsigned long long t0 = wall_clock64();
+                    while (__hip_atomic_fetch_add(d, Q.zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (wall_clock64() - t0 > Q.wait_ticks) {
+                            atomicOr(Q.error, 1);
+                            break;
+                        }
+                    }
+                }
+                // see the other tiles' stores: invalidates this CU's L1 and this XCD's L2
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+        }
+        const SubDev &S = subs[Q.sub_ids[slot]];
+        if (phase == 0)
+            sweep_tile<0, CAP, true>(S, local, coef, field, src, sh);
+        else if (phase == 1)
+            sweep_tile<1, CAP, true>(S, local, coef, field, src, sh);
+        else
+            sweep_tile<2, CAP, true>(S, local, coef, field, src, sh);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(done + phase * Q.count + slot, 1u, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_exchange(head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int i = 0; i < 3 * Q.count; ++i)
+                __hip_atomic_exchange(done + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_exchange(exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int AXIS>
 static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *subs,
                               const float2 *coef, float *field, const FusedSources &src,
@@ -404,6 +500,39 @@ static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *s
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_step_persistent(int cap_idx, int grid, const StepQueue &Q, const SubDev *subs,
+                                  const float2 *coef, float *field, const FusedSources &src,
+                                  hipStream_t st)
+{
+    if (Q.phase_start[3] <= 0 || grid <= 0) return hipSuccess;
+    const dim3 g(grid), b(128);
+    switch (cap_idx) {
+    case 0: hipLaunchKernelGGL(sweep_step_persistent<kCaps[0]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 1: hipLaunchKernelGGL(sweep_step_persistent<kCaps[1]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 2: hipLaunchKernelGGL(sweep_step_persistent<kCaps[2]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 3: hipLaunchKernelGGL(sweep_step_persistent<kCaps[3]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 4: hipLaunchKernelGGL(sweep_step_persistent<kCaps[4]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 5: hipLaunchKernelGGL(sweep_step_persistent<kCaps[5]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 6: hipLaunchKernelGGL(sweep_step_persistent<kCaps[6]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks)
+{
+    switch (cap_idx) {
+    case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[0]>, 128, 0);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[1]>, 128, 0);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[2]>, 128, 0);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[3]>, 128, 0);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[4]>, 128, 0);
+    case 5: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[5]>, 128, 0);
+    case 6: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[6]>, 128, 0);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,

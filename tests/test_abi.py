@@ -102,5 +102,27 @@ def test_fp32_rejects_overlong_lines_fp64_accepts():
             vb.vl_destroy(h)
 
 
+def test_options_on_the_host():
+    h = vb.vl_create(1, vb.VL_F32)
+    try:
+        assert vb.vl_get_option(h, vb.VL_OPT_FUSE_SOURCES) == 1
+        assert vb.vl_get_option(h, vb.VL_OPT_XCD_ORDER) == 1
+        vb.vl_set_option(h, vb.VL_OPT_XCD_ORDER, 0)
+        assert vb.vl_get_option(h, vb.VL_OPT_XCD_ORDER) == 0
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_FUSE_SOURCES, 2) == vb.VL_E_ARG
+        assert _code(vb.vl_set_option, h, 99, 0) == vb.VL_E_ARG
+        # the one-launch step is switched off for now and says so
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_STEP_MODE, vb.VL_MODE_PERSISTENT) == vb.VL_E_STATE
+        assert "switched off" in vb.vl_last_error()
+        assert vb.vl_get_option(h, vb.VL_OPT_STEP_MODE) == vb.VL_MODE_LAUNCHES
+    finally:
+        vb.vl_destroy(h)
+    h = vb.vl_create(1, vb.VL_F64)
+    try:
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_STEP_MODE, vb.VL_MODE_PERSISTENT) == vb.VL_E_ARG
+    finally:
+        vb.vl_destroy(h)
+
+
 def test_destroy_null_is_ok():
     vb.vl_destroy(None)

@@ -150,6 +150,98 @@ def test_fused_sources_equal_standalone_kernel():
     assert_close(fused[0], run_oracle(spec, 12), 1e-5, "fused sources")
 
 
+def _run_mode(specs, steps, mode, grid=0):
+    ctx = vb.Context(specs)
+    try:
+        ctx.set_option(vb.VL_OPT_STEP_MODE, mode)
+        ctx.set_option(vb.VL_OPT_PERSISTENT_GRID, grid)
+        ctx.step(steps)
+        ctx.sync()
+        return [ctx.get_field(k) for k in range(len(specs))]
+    finally:
+        ctx.close()
+
+
+ONE_LAUNCH_OFF = ("the one-launch step is switched off: its first GPU runs did not finish "
+                  "(grid = all resident workgroups), also with every wait bounded in time; "
+                  "the cause is not yet shown, so the case stays off the GPU")
+
+
+@pytest.mark.skip(reason=ONE_LAUNCH_OFF)
+@pytest.mark.parametrize("grid", [0, 1, 7, 300])
+def test_one_launch_step_equals_per_sweep_launches(grid):
+    """The one-launch step (queue over all tiles, per-volume waits) gives the
+    same bits as one launch per sweep, for any number of workgroups."""
+    wl = W.batched(n_sims=5, edge_range=(9, 75), cells_range=(100, 2000))
+    a = _run_mode(wl.sims, 6, vb.VL_MODE_LAUNCHES)
+    b = _run_mode(wl.sims, 6, vb.VL_MODE_PERSISTENT, grid)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert_close(b[2].astype(np.float64), run_oracle(wl.sims[2], 6), 1e-5, "one-launch batch")
+
+
+@pytest.mark.skip(reason=ONE_LAUNCH_OFF)
+def test_one_launch_step_long_lines():
+    spec = _spec((130, 66, 201), 2, "mixed", 2000, "f32", 61, layout="gaussian")
+    a = _run_mode([spec], 4, vb.VL_MODE_LAUNCHES)
+    b = _run_mode([spec], 4, vb.VL_MODE_PERSISTENT)
+    assert np.array_equal(a[0], b[0])
+
+
+def test_tuner_picks_a_mode_and_caches(tmp_path):
+    wl = W.batched(n_sims=8, edge_range=(20, 60), cells_range=(100, 500))
+    cache = str(tmp_path / "tune.txt")
+    ctx = vb.Context(wl.sims)
+    try:
+        ctx.tune(cache)
+        xcd = ctx.get_option(vb.VL_OPT_XCD_ORDER)
+        fuse = ctx.get_option(vb.VL_OPT_FUSE_SOURCES)
+        assert ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_LAUNCHES
+        words = open(cache).read().split()
+        assert len(words) == 5 and int(words[3]) == xcd and int(words[4]) == fuse
+        # a second context with the same shapes reads the choice back
+        ctx2 = vb.Context(wl.sims)
+        ctx2.set_option(vb.VL_OPT_XCD_ORDER, 1 - xcd)
+        ctx2.set_option(vb.VL_OPT_FUSE_SOURCES, 1 - fuse)
+        ctx2.tune(cache)
+        assert ctx2.get_option(vb.VL_OPT_XCD_ORDER) == xcd
+        assert ctx2.get_option(vb.VL_OPT_FUSE_SOURCES) == fuse
+        assert len(open(cache).read().split()) == 5
+        # the tuned context still computes the step correctly
+        for k, s in enumerate(wl.sims):
+            ctx2.set_field(k, s.rho0)
+        ctx2.step(3)
+        assert_close(ctx2.get_field(1).astype(np.float64), run_oracle(wl.sims[1], 3), 1e-5, "tuned")
+        ctx2.close()
+    finally:
+        ctx.close()
+
+
+@pytest.mark.skip(reason=ONE_LAUNCH_OFF)
+def test_one_launch_wait_limit_fails_loudly_not_hangs():
+    """With a zero wait limit a tile that has to wait gives up at once: the
+    step ends and vl_sync reports it (or nothing had to wait).  The next steps
+    with the default limit are correct again."""
+    wl = W.batched(n_sims=6, edge_range=(40, 90), cells_range=(100, 500))
+    ctx = vb.Context(wl.sims)
+    try:
+        ctx.set_option(vb.VL_OPT_STEP_MODE, vb.VL_MODE_PERSISTENT)
+        ctx.set_option(vb.VL_OPT_WAIT_LIMIT_US, 0)
+        ctx.step(3)
+        try:
+            ctx.sync()
+        except vb.VoxlodError as e:
+            assert e.code == vb.VL_E_STATE
+        ctx.set_option(vb.VL_OPT_WAIT_LIMIT_US, 2000000)
+        for k, s in enumerate(wl.sims):
+            ctx.set_field(k, s.rho0)
+        ctx.step(3)
+        ctx.sync()
+        assert_close(ctx.get_field(0).astype(np.float64), run_oracle(wl.sims[0], 3), 1e-5, "after limit")
+    finally:
+        ctx.close()
+
+
 def test_batch_of_one_equals_single():
     wl = W.batched(n_sims=3, edge_range=(10, 40), cells_range=(50, 200))
     fields, _ = run_gpu(wl.sims, 7)
