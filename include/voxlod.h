@@ -130,6 +130,15 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
  * (the null stream; steps are then launched without a graph). */
 int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream);
 
+/* Change one simulation's D and lambda after vl_bind (n_sub values each, same
+ * limits as vl_set_substrates; n_sub must equal the count set before
+ * vl_finalize).  Recomputes that context's line-solve coefficients on the
+ * bound stream, ordered after work already queued there; the tile tables and
+ * cells are unchanged.  This is what a parameter-fitting loop calls between
+ * a gradient step and the next forward run. */
+int vl_update_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D,
+                         const double *lambda);
+
 int vl_field_offset(vl_ctx *ctx, int sim, size_t *elem_offset);
 int vl_volume_stride(vl_ctx *ctx, int sim, size_t *elems);
 
@@ -198,6 +207,28 @@ int vl_get_option(vl_ctx *ctx, int option, int *value);
  * keyed by precision, decay split and every volume's shape, so a second call
  * for the same shapes does no timing.  No-op for VL_F64. */
 int vl_tune(vl_ctx *ctx, const char *cache_path);
+
+/* Adjoint of n_steps steps (FP32 contexts; for VL_F64 both return VL_E_STATE).
+ * For a scalar loss L whose gradient with respect to the field after n_steps
+ * steps is grad_final (device, field layout, field_elems floats), computes
+ *   grad_rho0 (device, field layout; may be NULL)  dL/d(field now),
+ *   dD, dlambda (host, one double per volume, simulations in order and their
+ *     substrates in order; may be NULL)            dL/dD_s, dL/dlambda_s,
+ *   dS, dU (device doubles, per simulation its cells in upload order, each
+ *     cell's substrates in order; required when cells exist) dL/dS_is, dL/dU_is
+ *     (zero for cells outside the grid).
+ * The forward run starts from the current field, keeps a checkpoint every
+ * ckpt_every steps and replays each segment; the field is restored on return.
+ * Reverse of a step: the adjoint of the sources (cells walked backwards per
+ * voxel, FP64), then of the z, y and x solves in that order (the line matrices
+ * are symmetric, so each is the same split solve) with the Dirichlet adjoint
+ * folded in; parameter sums are FP64 and taken in a fixed order.
+ * The caller allocates the adjoint workspace of vl_adjoint_workspace's size
+ * (256-byte aligned device memory).  Synchronises the stream. */
+int vl_adjoint_workspace(vl_ctx *ctx, int n_steps, int ckpt_every, size_t *bytes);
+int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace,
+               const void *grad_final, void *grad_rho0, double *dD, double *dlambda,
+               double *dS, double *dU);
 
 /* Per-kernel timing.  While enabled, vl_step launches without a graph and
  * brackets every kernel with HIP events on the bound stream.

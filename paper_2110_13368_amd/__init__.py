@@ -3,4 +3,4 @@
 Importing the package loads nothing; the HIP library is loaded on first use by
 ``paper_2110_13368_amd.binding`` and a missing or unloadable library raises.
 """
-__all__ = ["binding", "workloads"]
+__all__ = ["autograd", "binding", "workloads"]

@@ -57,6 +57,9 @@ SIGNATURES = {
     "vl_set_option": (_i, [_vp, _i, _i]),
     "vl_get_option": (_i, [_vp, _i, _ip]),
     "vl_tune": (_i, [_vp, C.c_char_p]),
+    "vl_update_substrates": (_i, [_vp, _i, _i, _dp, _dp]),
+    "vl_adjoint_workspace": (_i, [_vp, _i, _i, C.POINTER(_sz)]),
+    "vl_adjoint": (_i, [_vp, _i, _i, _vp, _vp, _vp, _dp, _dp, _vp, _vp]),
     "vl_set_profiling": (_i, [_vp, _i]),
     "vl_kernel_stats": (_i, [_vp, _i, C.POINTER(C.c_longlong), _dp]),
 }
@@ -154,6 +157,12 @@ def vl_bind(ctx, field_ptr: int, workspace_ptr: int, stream_ptr: int) -> None:
     _check(lib().vl_bind(ctx, _vp(field_ptr), _vp(workspace_ptr), _vp(stream_ptr or None)), "vl_bind")
 
 
+def vl_update_substrates(ctx, sim, D, lam) -> None:
+    D = _f64(D)
+    lam = _f64(lam, len(D))
+    _check(lib().vl_update_substrates(ctx, sim, len(D), _p(D), _p(lam)), "vl_update_substrates")
+
+
 def vl_field_offset(ctx, sim) -> int:
     o = _sz(0)
     _check(lib().vl_field_offset(ctx, int(sim), C.byref(o)), "vl_field_offset")
@@ -223,6 +232,23 @@ def vl_get_option(ctx, option: int) -> int:
 
 def vl_tune(ctx, cache_path: Optional[str] = None) -> None:
     _check(lib().vl_tune(ctx, cache_path.encode() if cache_path else None), "vl_tune")
+
+
+def vl_adjoint_workspace(ctx, n_steps: int, ckpt_every: int) -> int:
+    b = _sz(0)
+    _check(lib().vl_adjoint_workspace(ctx, int(n_steps), int(ckpt_every), C.byref(b)), "vl_adjoint_workspace")
+    return int(b.value)
+
+
+def vl_adjoint(ctx, n_steps: int, ckpt_every: int, ws_ptr: int, grad_final_ptr: int,
+               grad_rho0_ptr: int, n_volumes: int, dS_ptr: int, dU_ptr: int):
+    """Returns host arrays (dD, dlambda), one entry per volume."""
+    dD = np.zeros(n_volumes)
+    dl = np.zeros(n_volumes)
+    _check(lib().vl_adjoint(ctx, int(n_steps), int(ckpt_every), _vp(ws_ptr), _vp(grad_final_ptr),
+                            _vp(grad_rho0_ptr or None), _p(dD), _p(dl), _vp(dS_ptr or None),
+                            _vp(dU_ptr or None)), "vl_adjoint")
+    return dD, dl
 
 
 def vl_set_profiling(ctx, enable: bool) -> None:
@@ -319,6 +345,9 @@ class Context:
         return self.field.as_strided((s.n_sub, nz, ny, nx), (self.strides[k], nx * ny, nx, 1),
                                      self.offsets[k])
 
+    def update_substrates(self, k: int, D, lam) -> None:
+        vl_update_substrates(self.h, k, D, lam)
+
     def upload_cells(self, k: int, cells) -> int:
         return vl_upload_cells(self.h, k, cells.pos, cells.V, cells.S, cells.U, cells.rho_star,
                                self.sims[k].n_sub)
@@ -345,6 +374,58 @@ class Context:
     def tune(self, cache_path: Optional[str] = None) -> None:
         """Pick the step mode and launch size by timing (overwrites the field)."""
         vl_tune(self.h, cache_path)
+
+    def to_field_layout(self, arrays):
+        """Device tensor of the whole field (padded volumes) from one
+        (n_sub, nz, ny, nx) array per simulation."""
+        t = self.torch.zeros(self.field_elems, dtype=self.dtype, device=self.device)
+        for k, a in enumerate(arrays):
+            s = self.sims[k]
+            nx, ny, nz = s.shape
+            view = t.as_strided((s.n_sub, nz, ny, nx), (self.strides[k], nx * ny, nx, 1), self.offsets[k])
+            view.copy_(self.torch.as_tensor(a).to(self.device, self.dtype))
+        return t
+
+    def from_field_layout(self, t, k: int):
+        s = self.sims[k]
+        nx, ny, nz = s.shape
+        return t.as_strided((s.n_sub, nz, ny, nx), (self.strides[k], nx * ny, nx, 1), self.offsets[k])
+
+    def adjoint_flat(self, n_steps: int, ckpt_every: int, grad_final):
+        """vl_adjoint on flat tensors: grad_final in the field layout; returns
+        grad_rho0 (field layout), dD and dlambda (float64, one per volume) and
+        dS, dU (float64, per simulation its cells x n_sub, concatenated)."""
+        torch = self.torch
+        nbytes = vl_adjoint_workspace(self.h, n_steps, ckpt_every)
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        g = grad_final.to(self.device, self.dtype).contiguous()
+        if g.numel() != self.field_elems:
+            raise ValueError(f"grad_final must hold {self.field_elems} elements")
+        g0 = torch.zeros_like(g)
+        total = sum(s.cells.n * s.n_sub for s in self.sims)
+        dS = torch.zeros(max(total, 1), dtype=torch.float64, device=self.device)
+        dU = torch.zeros(max(total, 1), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        nvol = sum(s.n_sub for s in self.sims)
+        dD, dl = vl_adjoint(self.h, n_steps, ckpt_every, ws.data_ptr(), g.data_ptr(), g0.data_ptr(), nvol,
+                            dS.data_ptr(), dU.data_ptr())
+        return g0, torch.from_numpy(dD), torch.from_numpy(dl), dS[:total], dU[:total]
+
+    def adjoint(self, n_steps: int, ckpt_every: int, grad_final):
+        """Gradients of a loss whose gradient w.r.t. the field after n_steps
+        from the current field is grad_final (one array per simulation).
+        Returns per simulation: grad_rho0 (device tensor), dD, dlambda (numpy),
+        dS, dU (device tensors, cells x n_sub)."""
+        g0, dD, dl, dS, dU = self.adjoint_flat(n_steps, ckpt_every, self.to_field_layout(grad_final))
+        out, v, c = [], 0, 0
+        for k, s in enumerate(self.sims):
+            nc = s.cells.n * s.n_sub
+            out.append({"rho0": self.from_field_layout(g0, k).clone(), "D": dD[v:v + s.n_sub].numpy(),
+                        "lambda": dl[v:v + s.n_sub].numpy(),
+                        "S": dS[c:c + nc].reshape(s.cells.n, s.n_sub), "U": dU[c:c + nc].reshape(s.cells.n, s.n_sub)})
+            v += s.n_sub
+            c += nc
+        return out
 
     def set_profiling(self, on: bool) -> None:
         vl_set_profiling(self.h, on)

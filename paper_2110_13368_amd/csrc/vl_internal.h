@@ -91,9 +91,32 @@ hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
                                double2 *coef64, SubDev *subs_rw, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
+// raw (may be null, same layout as the field) receives each solve's output
+// before the Dirichlet projection, for the adjoint's replay.
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
-                            const SubDev *subs, const float2 *coef, float *field,
+                            const SubDev *subs, const float2 *coef, float *field, float *raw,
                             const FusedSources &src, hipStream_t st);
+
+// a9: adjoint sweep along axis, in place on w (same layout as the field).  The
+// Dirichlet adjoint (zero at Dirichlet voxels) is applied on load and store;
+// raw holds the forward solve's output.  Per tile, partials[3*tile + k] get
+// k = 0: w_out^T K y, 1: -w_out^T y, 2: w_in^T y (x sweep only).
+hipError_t launch_adjoint_sweep(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,
+                                const float2 *coef, float *w, const float *raw, double *partials,
+                                hipStream_t st);
+// totals[3*(3*q + axis) + k] += the partials of volume q's tiles, in tile order.
+hipError_t launch_reduce_partials(const SweepLaunch &L, int axis, const double *partials,
+                                  double *totals, hipStream_t st);
+// Adjoint of the sources of every simulation (FP64 arithmetic): w at occupied
+// voxels walks back through each voxel's cells; dS, dU (per cell and
+// substrate, in upload order) accumulate.
+hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *occ_prefix,
+                                  int total_occ, int max_ns, const SubDev *subs,
+                                  const int *occ_vox_v, const int *seg_start,
+                                  const double2 *ab, const double *krs, const double *kcell,
+                                  const int *cell_of, const float *r8, float *w,
+                                  const int *cell_out_base, double *dS, double *dU,
+                                  hipStream_t st);
 
 // a8: the whole step as one persistent launch of `grid` workgroups.
 hipError_t launch_step_persistent(int cap_idx, int grid, const StepQueue &Q, const SubDev *subs,
@@ -123,7 +146,8 @@ hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start,
                              int n_occ, int ns, const double *V, const double *S,
                              const double *U, const double *RS, double dt, double vvox,
-                             const int *pos, float2 *comp32, double2 *ab64, hipStream_t st);
+                             const int *pos, float2 *comp32, double2 *ab64, double *krs,
+                             double *kcell, int *cell_of, hipStream_t st);
 hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
                               unsigned long long *zkeys, int *occ_vox, int *pos, int *line_start,
                               hipStream_t st);

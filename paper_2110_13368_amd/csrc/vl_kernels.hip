@@ -446,7 +446,9 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
                                   const double *__restrict__ V, const double *__restrict__ S,
                                   const double *__restrict__ U, const double *__restrict__ RS,
                                   double dt, double vvox, const int *__restrict__ pos,
-                                  float2 *__restrict__ comp32, double2 *__restrict__ ab64)
+                                  float2 *__restrict__ comp32, double2 *__restrict__ ab64,
+                                  double *__restrict__ krs, double *__restrict__ kcell,
+                                  int *__restrict__ cell_of)
 {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)n_occ * ns) return;
@@ -460,6 +462,9 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
         const double a = k * S[q] * RS[q];
         const double b = 1.0 + k * (S[q] + U[q]);
         if (ab64) ab64[(size_t)p * ns + s] = make_double2(a, b);
+        if (krs) krs[(size_t)p * ns + s] = k * RS[q];
+        if (s == 0 && kcell) kcell[p] = k;
+        if (s == 0 && cell_of) cell_of[p] = i;
         A = A + a * B;
         B = B * b;
     }
@@ -469,12 +474,12 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, int n_occ, int ns,
                              const double *V, const double *S, const double *U, const double *RS,
                              double dt, double vvox, const int *pos, float2 *comp32, double2 *ab64,
-                             hipStream_t st)
+                             double *krs, double *kcell, int *cell_of, hipStream_t st)
 {
     const long long total = (long long)n_occ * ns;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(composites_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys,
-                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, ab64);
+                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, ab64, krs, kcell, cell_of);
     return hipGetLastError();
 }
 

@@ -119,6 +119,7 @@ struct vl_ctx {
     size_t o_pos = 0, o_V = 0, o_S = 0, o_U = 0, o_RS = 0, o_keys = 0, o_seg_id = 0;
     size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
     size_t o_zkeys = 0, o_occ_tmp = 0, o_pos_idx = 0, o_line_start = 0;
+    size_t o_krs = 0, o_kcell = 0, o_cell_of = 0, o_occ_vox_v = 0;
     size_t n_coef32 = 0, n_coef64 = 0;
 
     char *ws = nullptr;
@@ -270,7 +271,7 @@ int enqueue_step(vl_ctx *ctx)
                                   ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
                                   ctx->xcd_order ? 1 : 0};
                 rc = timed(ctx, VL_K_SWEEP_X + axis, [&] {
-                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, src, st);
+                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, nullptr, src, st);
                 });
                 if (rc) return rc;
             }
@@ -334,7 +335,7 @@ int upload_cell_tables(vl_ctx *ctx)
     std::vector<int> prefix(ctx->n_sims + 1, 0);
     for (int k = 0; k < ctx->n_sims; ++k) {
         const SimHost &s = ctx->sims[k];
-        cells[k] = vl::SimCells{s.sub0, s.ns, s.n_occ, s.occ_base, 0, s.comp_base, s.ab_base, s.zl_base};
+        cells[k] = vl::SimCells{s.sub0, s.ns, s.n_occ, s.occ_base, s.occ_base, s.comp_base, s.ab_base, s.zl_base};
         prefix[k + 1] = prefix[k] + s.n_occ;
     }
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_cells, cells.data(), cells.size() * sizeof(vl::SimCells),
@@ -459,6 +460,16 @@ int vl_reserve_cells(vl_ctx *ctx, int sim, int max_cells)
     return VL_OK;
 }
 
+// Coupling c_a = dt*D/h_a^2 per axis, and the decay as either a diagonal
+// shift sigma = lambda*dt/3 in every solve or one factor 1/(1+lambda*dt)
+// after the x solve.
+static void set_rates(SubDev &d, const SimHost &s, int q, double dt, int decay)
+{
+    for (int a = 0; a < 3; ++a) d.c[a] = dt * s.D[q] / (s.h[a] * s.h[a]);
+    d.sigma = decay == VL_DECAY_THIRDS ? s.lam[q] * dt / 3.0 : 0.0;
+    d.fdec = decay == VL_DECAY_ONCE ? 1.0 / (1.0 + s.lam[q] * dt) : 1.0;
+}
+
 int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_bytes)
 {
     if (int rc = check_ctx(ctx)) return rc;
@@ -490,7 +501,6 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             d.vol = s.nvox();
             for (int a = 0; a < 3; ++a) {
                 d.n[a] = s.n[a];
-                d.c[a] = dt * s.D[q] / (s.h[a] * s.h[a]);
                 d.coef64[a] = (int)c64;
                 d.coef32[a] = (int)c32;
                 c64 += (size_t)s.n[a];
@@ -498,8 +508,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             }
             d.sim = k;
             d.sub = q;
-            d.sigma = ctx->decay == VL_DECAY_THIRDS ? s.lam[q] * dt / 3.0 : 0.0;
-            d.fdec = ctx->decay == VL_DECAY_ONCE ? 1.0 / (1.0 + s.lam[q] * dt) : 1.0;
+            set_rates(d, s, q, dt, ctx->decay);
             for (int f = 0; f < 6; ++f) {
                 if (s.bc_kind[(size_t)q * 6 + f] == VL_DIRICHLET) d.dir_mask |= 1 << f;
                 d.dval64[f] = s.bc_val[(size_t)q * 6 + f];
@@ -663,7 +672,14 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_occ_vox = take(sizeof(int) * ctx->cap_total);
     ctx->o_seg_start = take(sizeof(int) * ctx->cap_total);
     ctx->o_comp = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->comp_total : 0);
-    ctx->o_ab = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->comp_total : 0);
+    ctx->o_ab = take(sizeof(double2) * ctx->comp_total);
+    // per sorted cell (FP32 path, for the adjoint): k, k rho*, upload index;
+    // and the occupied voxels in voxel order
+    const bool adj = ctx->precision == VL_F32;
+    ctx->o_krs = take(adj ? sizeof(double) * ctx->comp_total : 0);
+    ctx->o_kcell = take(adj ? sizeof(double) * ctx->cap_total : 0);
+    ctx->o_cell_of = take(adj ? sizeof(int) * ctx->cap_total : 0);
+    ctx->o_occ_vox_v = take(adj ? sizeof(int) * ctx->cap_total : 0);
     ctx->o_pos = take(sizeof(double) * 3 * ctx->stage_cells);
     ctx->o_V = take(sizeof(double) * ctx->stage_cells);
     ctx->o_S = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
@@ -727,6 +743,32 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
     }
     ctx->bound = true;
     if (int rc = upload_cell_tables(ctx)) return rc;
+    VL_HIP(hipStreamSynchronize(st));
+    return VL_OK;
+}
+
+int vl_update_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D, const double *lambda)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    SimHost &h = ctx->sims[sim];
+    if (n_sub != h.ns) return fail(VL_E_ARG, "n_sub differs from the count set before vl_finalize");
+    if (!D || !lambda) return fail(VL_E_ARG, "D and lambda must not be null");
+    for (int s = 0; s < n_sub; ++s)
+        if (!(D[s] >= 0) || !(lambda[s] >= 0) || !std::isfinite(D[s]) || !std::isfinite(lambda[s]))
+            return fail(VL_E_ARG, "D and lambda must be finite and >= 0");
+    h.D.assign(D, D + n_sub);
+    h.lam.assign(lambda, lambda + n_sub);
+    for (int q = 0; q < n_sub; ++q) set_rates(ctx->subs[h.sub0 + q], h, q, ctx->dt, ctx->decay);
+    hipStream_t st = ctx->stream;
+    const size_t first = (size_t)h.sub0;
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_subs + sizeof(SubDev) * first, ctx->subs.data() + first,
+                          sizeof(SubDev) * n_sub, hipMemcpyHostToDevice, st));
+    VL_HIP(vl::launch_coefficients(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(),
+                                   ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
+                                   ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
+                                   ctx->at<SubDev>(ctx->o_subs), st));
+    // the host copy of the descriptors must outlive the asynchronous upload
     VL_HIP(hipStreamSynchronize(st));
     return VL_OK;
 }
@@ -859,7 +901,7 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
         // FP32: occupied voxels first in voxel order (temporary), then
         // re-ordered by z-line for the sources fused into the z sweep.
         const bool zorder = ctx->precision == VL_F32;
-        int *occ_v = zorder ? ctx->at<int>(ctx->o_occ_tmp) : ctx->at<int>(ctx->o_occ_vox) + s.occ_base;
+        int *occ_v = zorder ? ctx->at<int>(ctx->o_occ_vox_v) + s.occ_base : ctx->at<int>(ctx->o_occ_vox) + s.occ_base;
         VL_HIP(vl::launch_segments(keys, n_in, ctx->at<int>(ctx->o_seg_id), occ_v,
                                    ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters + 1, st));
         VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
@@ -878,7 +920,10 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
                                      ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S),
                                      ctx->at<double>(ctx->o_U), ctx->at<double>(ctx->o_RS), ctx->dt, vvox,
                                      pos, zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
-                                     zorder ? nullptr : ctx->at<double2>(ctx->o_ab) + s.ab_base, st));
+                                     ctx->at<double2>(ctx->o_ab) + s.ab_base,
+                                     zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
+                                     zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
+                                     zorder ? ctx->at<int>(ctx->o_cell_of) + s.occ_base : nullptr, st));
     }
     s.n_occ = n_occ;
     s.n_out = n_out;
@@ -1153,6 +1198,184 @@ int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms
     if (launches) *launches = ctx->k_launches[kind];
     if (total_ms) *total_ms = ctx->k_ms[kind];
     return VL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (a9).  Workspace: checkpoints every K steps, the step starts of one
+// segment, the raw outputs of the three solves and the field before the
+// sources for the step being reversed, the adjoint field, per-tile partial
+// sums and per-volume totals.
+
+struct AdjLayout {
+    size_t ck, seg, raw[3], r8, w, part, totals, out_base, bytes;
+    int nseg, K;
+};
+
+static AdjLayout adj_layout(const vl_ctx *ctx, int n_steps, int K)
+{
+    AdjLayout a{};
+    a.K = K;
+    a.nseg = n_steps > 0 ? (n_steps + K - 1) / K : 1;
+    const size_t F = round_up(ctx->field_elems * sizeof(float), 256);
+    size_t max_tiles = 1;
+    for (const Launch &L : ctx->launches) max_tiles = std::max(max_tiles, (size_t)L.total_tiles);
+    size_t w = 0;
+    a.ck = w;
+    w += F * a.nseg;
+    a.seg = w;
+    w += F * K;
+    for (int i = 0; i < 3; ++i) {
+        a.raw[i] = w;
+        w += F;
+    }
+    a.r8 = w;
+    w += F;
+    a.w = w;
+    w += F;
+    a.part = w;
+    w += round_up(sizeof(double) * 3 * max_tiles, 256);
+    a.totals = w;
+    w += round_up(sizeof(double) * 9 * ctx->subs.size(), 256);
+    a.out_base = w;
+    w += round_up(sizeof(int) * (ctx->n_sims + 1), 256);
+    a.bytes = w;
+    return a;
+}
+
+int vl_adjoint_workspace(vl_ctx *ctx, int n_steps, int ckpt_every, size_t *bytes)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->finalized) return fail(VL_E_STATE, "call vl_finalize first");
+    if (ctx->precision != VL_F32) return fail(VL_E_STATE, "the adjoint runs on the FP32 path");
+    if (n_steps < 0 || ckpt_every < 1) return fail(VL_E_ARG, "n_steps >= 0 and ckpt_every >= 1 required");
+    if (!bytes) return fail(VL_E_ARG, "bytes is null");
+    *bytes = adj_layout(ctx, n_steps, std::min(ckpt_every, std::max(n_steps, 1))).bytes;
+    return VL_OK;
+}
+
+// One step replayed from the field, keeping each solve's raw output and the
+// field before the sources.
+static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
+{
+    hipStream_t st = ctx->stream;
+    const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
+    const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+    float *field = (float *)ctx->field;
+    const vl::FusedSources nosrc{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
+                                 ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0};
+    for (int axis = 0; axis < 3; ++axis)
+        for (const Launch &L : ctx->launches) {
+            if (L.axis != axis) continue;
+            vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
+                              L.count, L.total_tiles, 1};
+            VL_HIP(vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
+                                        nosrc, st));
+        }
+    VL_HIP(hipMemcpyAsync(aws + A.r8, field, ctx->field_elems * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return VL_OK;
+}
+
+int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, const void *grad_final_dev,
+               void *grad_rho0_dev, double *dD, double *dlambda, double *dS_dev, double *dU_dev)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    if (ctx->precision != VL_F32) return fail(VL_E_STATE, "the adjoint runs on the FP32 path");
+    if (n_steps < 0 || ckpt_every < 1) return fail(VL_E_ARG, "n_steps >= 0 and ckpt_every >= 1 required");
+    if (!adj_workspace || !grad_final_dev) return fail(VL_E_ARG, "workspace and grad_final must not be null");
+    if (reinterpret_cast<uintptr_t>(adj_workspace) & 255) return fail(VL_E_ARG, "workspace must be 256-byte aligned");
+    long long n_cells_sub = 0;
+    for (const SimHost &s : ctx->sims) n_cells_sub += (long long)s.n_cells * s.ns;
+    if (n_cells_sub > 0 && (!dS_dev || !dU_dev)) return fail(VL_E_ARG, "dS and dU are required when cells exist");
+    if (ctx->profiling && !ctx->recs.empty())
+        if (int rc = collect_events(ctx)) return rc;
+    const bool was_profiling = ctx->profiling;
+    ctx->profiling = false;
+    const int K = std::min(ckpt_every, std::max(n_steps, 1));
+    const AdjLayout A = adj_layout(ctx, n_steps, K);
+    char *aws = (char *)adj_workspace;
+    hipStream_t st = ctx->stream;
+    const size_t fbytes = ctx->field_elems * sizeof(float);
+    const size_t F = round_up(fbytes, 256);
+    int rc = VL_OK;
+    auto run = [&]() -> int {
+        // forward with checkpoints
+        for (int t = 0; t < n_steps; ++t) {
+            if (t % K == 0)
+                VL_HIP(hipMemcpyAsync(aws + A.ck + F * (t / K), ctx->field, fbytes, hipMemcpyDeviceToDevice, st));
+            if (int r = enqueue_step(ctx)) return r;
+        }
+        if (n_steps == 0)
+            VL_HIP(hipMemcpyAsync(aws + A.ck, ctx->field, fbytes, hipMemcpyDeviceToDevice, st));
+        VL_HIP(hipMemcpyAsync(aws + A.w, grad_final_dev, fbytes, hipMemcpyDeviceToDevice, st));
+        VL_HIP(hipMemsetAsync(aws + A.totals, 0, sizeof(double) * 9 * ctx->subs.size(), st));
+        std::vector<int> ob(ctx->n_sims + 1, 0);
+        for (int k = 0; k < ctx->n_sims; ++k) ob[k + 1] = ob[k] + ctx->sims[k].n_cells * ctx->sims[k].ns;
+        VL_HIP(hipMemcpyAsync(aws + A.out_base, ob.data(), sizeof(int) * ob.size(), hipMemcpyHostToDevice, st));
+        if (n_cells_sub > 0) {
+            VL_HIP(hipMemsetAsync(dS_dev, 0, sizeof(double) * n_cells_sub, st));
+            VL_HIP(hipMemsetAsync(dU_dev, 0, sizeof(double) * n_cells_sub, st));
+        }
+        int total_occ = 0;
+        for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+        const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
+        const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+        float *w = (float *)(aws + A.w);
+        for (int seg = A.nseg - 1; seg >= 0 && n_steps > 0; --seg) {
+            const int t0 = seg * K, t1 = std::min(t0 + K, n_steps);
+            VL_HIP(hipMemcpyAsync(ctx->field, aws + A.ck + F * seg, fbytes, hipMemcpyDeviceToDevice, st));
+            for (int t = t0; t < t1; ++t) {
+                VL_HIP(hipMemcpyAsync(aws + A.seg + F * (t - t0), ctx->field, fbytes, hipMemcpyDeviceToDevice, st));
+                if (t + 1 < t1)
+                    if (int r = enqueue_step(ctx)) return r;
+            }
+            for (int t = t1 - 1; t >= t0; --t) {
+                VL_HIP(hipMemcpyAsync(ctx->field, aws + A.seg + F * (t - t0), fbytes, hipMemcpyDeviceToDevice, st));
+                if (int r = replay_step(ctx, aws, A)) return r;
+                VL_HIP(vl::launch_sources_adjoint(
+                    ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims, ctx->at<int>(ctx->o_occ_prefix), total_occ,
+                    ctx->max_ns, subs, ctx->at<int>(ctx->o_occ_vox_v), ctx->at<int>(ctx->o_seg_start),
+                    ctx->at<double2>(ctx->o_ab), ctx->at<double>(ctx->o_krs), ctx->at<double>(ctx->o_kcell),
+                    ctx->at<int>(ctx->o_cell_of), (const float *)(aws + A.r8), w, (const int *)(aws + A.out_base),
+                    dS_dev, dU_dev, st));
+                for (int axis = 2; axis >= 0; --axis)
+                    for (const Launch &L : ctx->launches) {
+                        if (L.axis != axis) continue;
+                        vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
+                                          ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles, 0};
+                        VL_HIP(vl::launch_adjoint_sweep(axis, L.cap_idx, d, subs, coef, w,
+                                                        (const float *)(aws + A.raw[axis]),
+                                                        (double *)(aws + A.part), st));
+                        VL_HIP(vl::launch_reduce_partials(d, axis, (const double *)(aws + A.part),
+                                                          (double *)(aws + A.totals), st));
+                    }
+            }
+        }
+        if (grad_rho0_dev)
+            VL_HIP(hipMemcpyAsync(grad_rho0_dev, w, fbytes, hipMemcpyDeviceToDevice, st));
+        VL_HIP(hipMemcpyAsync(ctx->field, aws + A.ck, fbytes, hipMemcpyDeviceToDevice, st));
+        std::vector<double> T(9 * ctx->subs.size());
+        VL_HIP(hipMemcpyAsync(T.data(), aws + A.totals, sizeof(double) * T.size(), hipMemcpyDeviceToHost, st));
+        VL_HIP(hipStreamSynchronize(st));
+        for (size_t q = 0; q < ctx->subs.size(); ++q) {
+            const SubDev &d = ctx->subs[q];
+            const SimHost &s = ctx->sims[d.sim];
+            const double fx = d.fdec;  // folded into the x solve's table
+            double gd = 0.0, gl = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double gc = T[3 * (3 * q + a) + 0] / (a == 0 ? fx : 1.0);
+                gd += gc * ctx->dt / (s.h[a] * s.h[a]);
+                if (ctx->decay == VL_DECAY_THIRDS) gl += T[3 * (3 * q + a) + 1] * ctx->dt / 3.0;
+            }
+            if (ctx->decay == VL_DECAY_ONCE) gl = -ctx->dt * fx * T[3 * (3 * q + 0) + 2];
+            if (dD) dD[q] = gd;
+            if (dlambda) dlambda[q] = gl;
+        }
+        return VL_OK;
+    };
+    rc = run();
+    ctx->profiling = was_profiling;
+    return rc;
 }
 
 }  // extern "C"

@@ -28,136 +28,18 @@
 // contiguous: they are moved through a 64x65 LDS block per 64 columns, loaded
 // with lanes along x and read back with lanes along the lines.  The half line
 // a lane owns stays in VGPRs (CAP values).
-#include "vl_internal.h"
+#include "vl_device.h"
 
 namespace vl {
 
-// Workgroup b runs on XCD b % 8; give each XCD a contiguous range of tiles so
-// that tiles sharing cache lines meet in the same L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nb)
-{
-    const int x = bid & 7, q = bid >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    return (x < rem) ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
-}
-
-// Largest k in [0, count) with prefix[k] <= tile.
-__device__ __forceinline__ int find_slot(const int *__restrict__ prefix, int count, int tile)
-{
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= tile)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-// Highest-numbered face whose bit is set in both masks, -1 if none.
-__device__ __forceinline__ int top_face(int mask)
-{
-    return mask ? 31 - __builtin_clz(mask) : -1;
-}
-
-__device__ __forceinline__ float face_value(const float (&d)[6], int f)
-{
-    float v = d[0];
-    v = (f == 1) ? d[1] : v;
-    v = (f == 2) ? d[2] : v;
-    v = (f == 3) ? d[3] : v;
-    v = (f == 4) ? d[4] : v;
-    v = (f == 5) ? d[5] : v;
-    return v;
-}
-
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Raw buffer access: the lane part of an offset stays in a VGPR, the
-// wave-uniform row part goes in an SGPR, so walking a line costs no vector
-// address arithmetic.  Offsets are in bytes from the resource base.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float *base, long long elems)
-{
-    const long long bytes = elems * 4;
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0,
-                                             (int)min(bytes, (long long)0x7fffffff), 0x00020000);
-}
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
-{
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
-}
-
-// Runs BODY for t = 0..CAP-1 with t < cnt, cnt wave-uniform: whole groups
-// of 8 without per-element tests.  Written as macros so that every register
-// index is a constant after unrolling (the array must never leave VGPRs).
-#define VL_FOR_UP(CAP_, cnt, t, BODY)                                                  \
-    _Pragma("unroll") for (int g_ = 0; g_ < (CAP_); g_ += 8)                           \
-    {                                                                                  \
-        if (g_ + 8 <= (cnt)) {                                                         \
-            _Pragma("unroll") for (int j_ = 0; j_ < 8; ++j_)                           \
-            {                                                                          \
-                const int t = g_ + j_;                                                 \
-                if (t < (CAP_)) { BODY }                                               \
-            }                                                                          \
-        } else if (g_ < (cnt)) {                                                       \
-            _Pragma("unroll") for (int j_ = 0; j_ < 8; ++j_)                           \
-            {                                                                          \
-                const int t = g_ + j_;                                                 \
-                if (t < (CAP_) && t < (cnt)) { BODY }                                  \
-            }                                                                          \
-        }                                                                              \
-    }
-// Same, t descending.
-#define VL_FOR_DOWN(CAP_, cnt, t, BODY)                                                \
-    _Pragma("unroll") for (int g_ = ((CAP_) + 7) / 8 * 8 - 8; g_ >= 0; g_ -= 8)        \
-    {                                                                                  \
-        if (g_ + 8 <= (cnt)) {                                                         \
-            _Pragma("unroll") for (int j_ = 7; j_ >= 0; --j_)                          \
-            {                                                                          \
-                const int t = g_ + j_;                                                 \
-                if (t < (CAP_)) { BODY }                                               \
-            }                                                                          \
-        } else if (g_ < (cnt)) {                                                       \
-            _Pragma("unroll") for (int j_ = 7; j_ >= 0; --j_)                          \
-            {                                                                          \
-                const int t = g_ + j_;                                                 \
-                if (t < (CAP_) && t < (cnt)) { BODY }                                  \
-            }                                                                          \
-        }                                                                              \
-    }
-
-// Waves per SIMD the register budget is sized for, by capacity class.
-__host__ __device__ constexpr int waves_for_cap(int cap)
-{
-    return cap <= 64 ? 4 : cap <= 128 ? 3 : cap <= 200 ? 2 : 1;
-}
-
-// LDS of one tile.  The x sweep needs the 64x65 staging block per wave; the
-// others only the exchange slots and the pivot table.
-template <int CAP, bool XSTAGE>
-struct TileLds {
-    float xch[2][kWave];
-    float2 piv[CAP];
-    float stage[XSTAGE ? 2 * 64 * 65 : 1];
-};
 
 // One tile of one sweep: 64 lines of volume S, tile index `local` within the
 // volume's tiles of this axis.  Called by every thread of a 128-thread
 // workgroup (it contains workgroup barriers).
 template <int AXIS, int CAP, bool XSTAGE>
 __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const float2 *__restrict__ coef,
-                                           float *__restrict__ field, const FusedSources &src,
-                                           TileLds<CAP, XSTAGE> &sh)
+                                           float *__restrict__ field, float *__restrict__ raw,
+                                           const FusedSources &src, TileLds<CAP, XSTAGE> &sh)
 {
     constexpr int kChunks = (CAP + 63) / 64;
     float(&xch)[2][kWave] = sh.xch;
@@ -315,6 +197,23 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
         v[t] = nxt;
     })
 
+    // ---- raw solve output before the Dirichlet projection (adjoint replay) ----
+    if (raw != nullptr) {
+        const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw + base, S.base + S.vol - base);
+        if (AXIS == 0) {
+            // each lane along its own x-line: uncoalesced, used only when replaying
+            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm);
+            const int col0 = top ? 0 : (n - 1) * 4;
+            const int cstep = top ? 4 : -4;
+            VL_FOR_UP(CAP, nel, t, bstore(rr, lane_b, col0 + t * cstep, v[t]);)
+        } else {
+            if (top) bstore(rr, lane_b, m * row_b, xm);
+            const int row0 = top ? 0 : (n - 1) * row_b;
+            const int step = top ? row_b : -row_b;
+            VL_FOR_UP(CAP, nel, t, bstore(rr, lane_b, row0 + t * step, v[t]);)
+        }
+    }
+
     // ---- Dirichlet projection after the solve ----
     if (__builtin_amdgcn_ballot_w64(wface >= 0) != 0) {
         const float wv = face_value(S.dval32, wface);
@@ -396,13 +295,13 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
 template <int AXIS, int CAP>
 __global__ void __launch_bounds__(128)
 sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
-          float *__restrict__ field, FusedSources src)
+          float *__restrict__ field, float *__restrict__ raw, FusedSources src)
 {
     __shared__ TileLds<CAP, AXIS == 0> sh;
     const int tile = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int slot = find_slot(L.tile_prefix, L.count, tile);
     const int local = tile - L.tile_prefix[slot];
-    sweep_tile<AXIS, CAP, AXIS == 0>(subs[L.sub_ids[slot]], local, coef, field, src, sh);
+    sweep_tile<AXIS, CAP, AXIS == 0>(subs[L.sub_ids[slot]], local, coef, field, raw, src, sh);
 }
 
 // The whole step in one launch.  Workgroups take tiles from one queue in the
@@ -461,11 +360,11 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const float2
         }
         const SubDev &S = subs[Q.sub_ids[slot]];
         if (phase == 0)
-            sweep_tile<0, CAP, true>(S, local, coef, field, src, sh);
+            sweep_tile<0, CAP, true>(S, local, coef, field, nullptr, src, sh);
         else if (phase == 1)
-            sweep_tile<1, CAP, true>(S, local, coef, field, src, sh);
+            sweep_tile<1, CAP, true>(S, local, coef, field, nullptr, src, sh);
         else
-            sweep_tile<2, CAP, true>(S, local, coef, field, src, sh);
+            sweep_tile<2, CAP, true>(S, local, coef, field, nullptr, src, sh);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
@@ -485,18 +384,18 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const float2
 
 template <int AXIS>
 static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *subs,
-                              const float2 *coef, float *field, const FusedSources &src,
+                              const float2 *coef, float *field, float *raw, const FusedSources &src,
                               hipStream_t st)
 {
     const dim3 grid(L.total_tiles), block(128);
     switch (cap_idx) {
-    case 0: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[0]>), grid, block, 0, st, L, subs, coef, field, src); break;
-    case 1: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[1]>), grid, block, 0, st, L, subs, coef, field, src); break;
-    case 2: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[2]>), grid, block, 0, st, L, subs, coef, field, src); break;
-    case 3: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[3]>), grid, block, 0, st, L, subs, coef, field, src); break;
-    case 4: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, field, src); break;
-    case 5: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, field, src); break;
-    case 6: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, field, src); break;
+    case 0: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[0]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 1: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[1]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 2: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[2]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 3: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[3]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 4: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 5: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 6: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -536,13 +435,13 @@ hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks)
 }
 
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,
-                            const float2 *coef, float *field, const FusedSources &src,
+                            const float2 *coef, float *field, float *raw, const FusedSources &src,
                             hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;
-    if (axis == 0) return launch_axis<0>(cap_idx, L, subs, coef, field, src, st);
-    if (axis == 1) return launch_axis<1>(cap_idx, L, subs, coef, field, src, st);
-    if (axis == 2) return launch_axis<2>(cap_idx, L, subs, coef, field, src, st);
+    if (axis == 0) return launch_axis<0>(cap_idx, L, subs, coef, field, raw, src, st);
+    if (axis == 1) return launch_axis<1>(cap_idx, L, subs, coef, field, raw, src, st);
+    if (axis == 2) return launch_axis<2>(cap_idx, L, subs, coef, field, raw, src, st);
     return hipErrorInvalidValue;
 }
 
