@@ -1,6 +1,6 @@
 """Benchmark of the LOD diffusion-decay step with cell sources on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config single|tumour|batched|plain]
+    python bench.py [--steps K] [--warmup W] [--config single|tumour|batched|plain|adjoint]
 
 A step is one full LOD step (x, y, z line solves with Dirichlet projection and
 decay folded in, then the cell sources) over every simulation of the
@@ -110,6 +110,110 @@ def cpu_baseline(wl, budget_s: float):
             "sample": sample, "seconds": round(t, 3)}
 
 
+def adjoint_cpu_baseline(wl, grads, budget_s: float):
+    """The FP64 oracle's adjoint (forward with checkpoints, reverse) on the
+    host cores, over as many steps of the same workload as fit the budget."""
+    import oracle
+    spec = wl.sims[0]
+    n, t = 2, 0.0
+    while True:
+        sim = oracle.from_spec(spec)
+        t0 = time.perf_counter()
+        sim.adjoint(n, grads[0])
+        t = time.perf_counter() - t0
+        sim.close()
+        if t > budget_s / 3 or n >= wl.steps:
+            break
+        n = min(wl.steps, 2 * n)
+    return {"value": spec.n_vox * spec.n_sub * n / t, "unit": "voxel-substrate steps reversed/s",
+            "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"adjoint of {n} steps of {'x'.join(map(str, spec.shape))} x {spec.n_sub} "
+                      f"with {spec.cells.n} cells", "seconds": round(t, 3)}
+
+
+def run_adjoint(args):
+    """Reverse-mode gradient of the differentiation workload: one vl_adjoint
+    call over --steps steps (default 200) with a checkpoint every 20 steps,
+    timed whole (its checkpointed forward, the segment replays and the reverse
+    steps).  value = voxel-substrate steps reversed per second."""
+    import torch
+    from paper_2110_13368_amd import binding as vb
+    from paper_2110_13368_amd import workloads as W
+    wl = W.differentiation()
+    n_steps = args.steps if args.steps_given else wl.steps
+    ckpt = args.ckpt_every
+    E = wl.voxel_substrates
+    print(f"bench: adjoint of {wl.name}: {E} voxel-substrates, {n_steps} steps, checkpoint every {ckpt}",
+          file=sys.stderr, flush=True)
+    ctx = vb.Context(wl.sims)
+    rng = np.random.default_rng(211013368 + 40)
+    grads = [rng.normal(size=s.field_shape) for s in wl.sims]
+    g = ctx.to_field_layout([a.astype(np.float32) for a in grads])
+    g0 = torch.zeros_like(g)
+    ncs = max(sum(s.cells.n * s.n_sub for s in wl.sims), 1)
+    dS = torch.zeros(ncs, dtype=torch.float64, device=ctx.device)
+    dU = torch.zeros(ncs, dtype=torch.float64, device=ctx.device)
+    nvol = sum(s.n_sub for s in wl.sims)
+
+    def call(n):
+        nb = vb.vl_adjoint_workspace(ctx.h, n, ckpt)
+        ws = call.ws if getattr(call, "ws", None) is not None and call.ws.numel() >= nb else \
+            torch.empty(max(nb, 256), dtype=torch.uint8, device=ctx.device)
+        call.ws = ws
+        torch.cuda.synchronize()
+        return vb.vl_adjoint(ctx.h, n, ckpt, ws.data_ptr(), g.data_ptr(), g0.data_ptr(), nvol,
+                             dS.data_ptr(), dU.data_ptr())
+
+    call(n_steps)  # allocates the workspace; warm-up
+    for _ in range(max(args.warmup, 0) // 20):
+        call(n_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dD, dl = call(n_steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = E * n_steps / elapsed
+    print(f"bench: adjoint of {n_steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+
+    ctx.set_profiling(True)
+    call(n_steps)
+    stats = ctx.kernel_stats()
+    ctx.set_profiling(False)
+    kinds = {k: v for k, v in stats.items() if v[0] > 0}
+    # algorithmic bytes per element and launch: a forward solve reads and
+    # writes the field; a replay also writes its raw output; a reverse solve
+    # reads the adjoint and the raw output and writes the adjoint; a copy
+    # reads and writes one field
+    per_elem = {"sweep_x": 8, "sweep_y": 8, "sweep_z": 8, "replay_x": 12, "replay_y": 12, "replay_z": 12,
+                "adjoint_x": 12, "adjoint_y": 12, "adjoint_z": 12, "adjoint_copy": 8}
+    dom = max((k for k in kinds if k in per_elem), key=lambda k: kinds[k][1])
+    launches, total_ms = kinds[dom]
+    avg_ms = total_ms / launches
+    alg = per_elem[dom] * E
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(alg / (avg_ms * 1e-3) / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(alg / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_ms": round(avg_ms, 5), "launches": launches, "bytes_per_launch": alg}
+    kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 5), "total_ms": round(v[1], 3)}
+               for k, v in kinds.items()}
+    ctx.close()
+    line = {
+        "metric": "adjoint: voxel-substrate steps reversed/s (checkpointed, FP32 with FP64 sums)",
+        "value": value, "unit": "voxel-substrate steps reversed/s", "n_gpus": 1, "steps": n_steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / n_steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded generators shaped like the paper's tumour workloads)",
+        "config": {"workload": wl.name, "voxel_substrates": E, "grid": list(wl.sims[0].shape),
+                   "n_sub": wl.sims[0].n_sub, "cells": int(wl.sims[0].cells.n), "ckpt_every": ckpt,
+                   "parallelism": "single-gpu"},
+        "gradients": {"dD": [float(x) for x in dD], "dlambda": [float(x) for x in dl]},
+        "roofline": roofline, "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = adjoint_cpu_baseline(wl, grads, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,12 +225,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-reference", action="store_true")
     ap.add_argument("--mode", default="tuned", choices=["tuned", "launches", "persistent"])
+    ap.add_argument("--ckpt-every", type=int, default=20)
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "batched simulations shard by simulation and a single grid by z-slabs, "
               "neither is built here.", file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "adjoint":
+        return run_adjoint(args)
 
     import torch
     from paper_2110_13368_amd import binding as vb

@@ -91,7 +91,17 @@ extern "C" {
 #define VL_K_DIRICHLET 4
 #define VL_K_DECAY 5
 #define VL_K_STEP 6 /* the one-launch step (VL_MODE_PERSISTENT) */
-#define VL_K_COUNT 7
+/* inside vl_adjoint (its forward steps count as the kinds above) */
+#define VL_K_REPLAY_X 7 /* forward solves that also keep their raw output */
+#define VL_K_REPLAY_Y 8
+#define VL_K_REPLAY_Z 9
+#define VL_K_ADJ_X 10 /* reverse solves with the parameter partial sums */
+#define VL_K_ADJ_Y 11
+#define VL_K_ADJ_Z 12
+#define VL_K_ADJ_SOURCES 13
+#define VL_K_ADJ_REDUCE 14
+#define VL_K_ADJ_COPY 15 /* checkpoint and state copies */
+#define VL_K_COUNT 16
 
 typedef struct vl_ctx vl_ctx;
 
@@ -231,7 +241,8 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace,
                double *dS, double *dU);
 
 /* Per-kernel timing.  While enabled, vl_step launches without a graph and
- * brackets every kernel with HIP events on the bound stream.
+ * brackets every kernel with HIP events on the bound stream; so does
+ * vl_adjoint.
  * vl_kernel_stats synchronises and reports, for one VL_K_* kind, the number
  * of launches and their summed duration since profiling was enabled. */
 int vl_set_profiling(vl_ctx *ctx, int enable);

@@ -13,8 +13,8 @@
 //   dL/dc     +=  w_out^T K y  = - sum_i (w_{i+1} - w_i)(y_{i+1} - y_i)
 //   dL/dsigma += -w_out^T y
 //   dL/dlambda (decay once) += -dt f^2 w_in^T y_x
-// summed over the lines of a volume in a fixed order (per lane, per wave,
-// per tile, then tiles in order), so results are deterministic.
+// summed in a fixed order (per lane, per wave, per tile over the reverse
+// steps, then the tiles of a volume in order), so results are deterministic.
 #include "vl_device.h"
 
 namespace vl {
@@ -220,7 +220,9 @@ __device__ __forceinline__ void adjoint_tile(const SubDev &S, int local, int til
         red[wave][2] = s_lam;
     }
     __syncthreads();
-    if (threadIdx.x < 3) part[3 * (size_t)tile + threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x];
+    // each tile owns its slots and the reverse steps run in stream order, so
+    // the running sum over steps needs no atomics
+    if (threadIdx.x < 3) part[3 * (size_t)tile + threadIdx.x] += red[0][threadIdx.x] + red[1][threadIdx.x];
 }
 
 template <int AXIS, int CAP>
@@ -287,7 +289,7 @@ hipError_t launch_reduce_partials(const SweepLaunch &L, int axis, const double *
 }
 
 // C^T at one occupied voxel and substrate.  The forward values after each
-// cell are rebuilt from the value before the sources (r8) and recovered on
+// cell are rebuilt from the value before the sources (rho) and recovered on
 // the way back as rho_{i-1} = rho_i b_i - a_i.  For cell i, with w the
 // adjoint of the value after it:
 //   abar = w/b_i,  bbar = -w rho_i/b_i,  w <- w/b_i,
@@ -312,7 +314,7 @@ __global__ void sources_adjoint_kernel(const SimCells *__restrict__ cells, int n
                                        const SubDev *__restrict__ subs, const int *__restrict__ occ_vox_v,
                                        const int *__restrict__ seg_start, const double2 *__restrict__ ab,
                                        const double *__restrict__ krs, const double *__restrict__ kcell,
-                                       const int *__restrict__ cell_of, const float *__restrict__ r8,
+                                       const int *__restrict__ cell_of, const float *__restrict__ rho,
                                        float *__restrict__ w, const int *__restrict__ out_base,
                                        double *__restrict__ dS, double *__restrict__ dU)
 {
@@ -326,7 +328,7 @@ __global__ void sources_adjoint_kernel(const SimCells *__restrict__ cells, int n
     const int v = occ_vox_v[C.occ_base + jl];
     const int p0 = seg_start[C.occ_base + jl], p1 = seg_start[C.occ_base + jl + 1];
     const long long at = subs[C.sub0 + s].base + v;
-    double r = r8[at];
+    double r = rho[at];
     for (int p = p0; p < p1; ++p) {
         const double2 e = ab[C.ab_base + (size_t)p * C.ns + s];
         r = (r + e.x) / e.y;
@@ -349,12 +351,12 @@ __global__ void sources_adjoint_kernel(const SimCells *__restrict__ cells, int n
 hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
                                   int max_ns, const SubDev *subs, const int *occ_vox_v,
                                   const int *seg_start, const double2 *ab, const double *krs,
-                                  const double *kcell, const int *cell_of, const float *r8, float *w,
+                                  const double *kcell, const int *cell_of, const float *rho, float *w,
                                   const int *cell_out_base, double *dS, double *dU, hipStream_t st)
 {
     if (total_occ <= 0) return hipSuccess;
     hipLaunchKernelGGL(sources_adjoint_kernel, dim3((total_occ + 127) / 128, max_ns), dim3(128), 0, st, cells,
-                       nsims, occ_prefix, total_occ, subs, occ_vox_v, seg_start, ab, krs, kcell, cell_of, r8, w,
+                       nsims, occ_prefix, total_occ, subs, occ_vox_v, seg_start, ab, krs, kcell, cell_of, rho, w,
                        cell_out_base, dS, dU);
     return hipGetLastError();
 }

@@ -114,7 +114,7 @@ hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *o
                                   int total_occ, int max_ns, const SubDev *subs,
                                   const int *occ_vox_v, const int *seg_start,
                                   const double2 *ab, const double *krs, const double *kcell,
-                                  const int *cell_of, const float *r8, float *w,
+                                  const int *cell_of, const float *rho, float *w,
                                   const int *cell_out_base, double *dS, double *dU,
                                   hipStream_t st);
 

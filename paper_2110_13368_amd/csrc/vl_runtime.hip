@@ -1207,7 +1207,9 @@ int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms
 // sums and per-volume totals.
 
 struct AdjLayout {
-    size_t ck, seg, raw[3], r8, w, part, totals, out_base, bytes;
+    size_t ck, seg, raw[3], w, part, totals, out_base, bytes;
+    std::vector<size_t> part_off;  // per sweep launch: its tiles' slots in part
+    size_t n_slots;
     int nseg, K;
 };
 
@@ -1217,8 +1219,12 @@ static AdjLayout adj_layout(const vl_ctx *ctx, int n_steps, int K)
     a.K = K;
     a.nseg = n_steps > 0 ? (n_steps + K - 1) / K : 1;
     const size_t F = round_up(ctx->field_elems * sizeof(float), 256);
-    size_t max_tiles = 1;
-    for (const Launch &L : ctx->launches) max_tiles = std::max(max_tiles, (size_t)L.total_tiles);
+    size_t n_slots = 0;
+    for (const Launch &L : ctx->launches) {
+        a.part_off.push_back(n_slots);
+        n_slots += 3 * (size_t)L.total_tiles;
+    }
+    a.n_slots = n_slots;
     size_t w = 0;
     a.ck = w;
     w += F * a.nseg;
@@ -1228,12 +1234,10 @@ static AdjLayout adj_layout(const vl_ctx *ctx, int n_steps, int K)
         a.raw[i] = w;
         w += F;
     }
-    a.r8 = w;
-    w += F;
     a.w = w;
     w += F;
     a.part = w;
-    w += round_up(sizeof(double) * 3 * max_tiles, 256);
+    w += round_up(sizeof(double) * std::max<size_t>(n_slots, 1), 256);
     a.totals = w;
     w += round_up(sizeof(double) * 9 * ctx->subs.size(), 256);
     a.out_base = w;
@@ -1253,8 +1257,8 @@ int vl_adjoint_workspace(vl_ctx *ctx, int n_steps, int ckpt_every, size_t *bytes
     return VL_OK;
 }
 
-// One step replayed from the field, keeping each solve's raw output and the
-// field before the sources.
+// One step replayed from the field without its sources, keeping each
+// solve's raw output; the field is left as it was before the sources.
 static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
 {
     hipStream_t st = ctx->stream;
@@ -1268,10 +1272,12 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
             if (L.axis != axis) continue;
             vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
                               L.count, L.total_tiles, 1};
-            VL_HIP(vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
-                                        nosrc, st));
+            if (int rc = timed(ctx, VL_K_REPLAY_X + axis, [&] {
+                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
+                                                nosrc, st);
+                }))
+                return rc;
         }
-    VL_HIP(hipMemcpyAsync(aws + A.r8, field, ctx->field_elems * sizeof(float), hipMemcpyDeviceToDevice, st));
     return VL_OK;
 }
 
@@ -1287,95 +1293,111 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
     long long n_cells_sub = 0;
     for (const SimHost &s : ctx->sims) n_cells_sub += (long long)s.n_cells * s.ns;
     if (n_cells_sub > 0 && (!dS_dev || !dU_dev)) return fail(VL_E_ARG, "dS and dU are required when cells exist");
-    if (ctx->profiling && !ctx->recs.empty())
-        if (int rc = collect_events(ctx)) return rc;
-    const bool was_profiling = ctx->profiling;
-    ctx->profiling = false;
     const int K = std::min(ckpt_every, std::max(n_steps, 1));
     const AdjLayout A = adj_layout(ctx, n_steps, K);
     char *aws = (char *)adj_workspace;
     hipStream_t st = ctx->stream;
     const size_t fbytes = ctx->field_elems * sizeof(float);
     const size_t F = round_up(fbytes, 256);
-    int rc = VL_OK;
-    auto run = [&]() -> int {
-        // forward with checkpoints
-        for (int t = 0; t < n_steps; ++t) {
-            if (t % K == 0)
-                VL_HIP(hipMemcpyAsync(aws + A.ck + F * (t / K), ctx->field, fbytes, hipMemcpyDeviceToDevice, st));
-            if (int r = enqueue_step(ctx)) return r;
-        }
-        if (n_steps == 0)
-            VL_HIP(hipMemcpyAsync(aws + A.ck, ctx->field, fbytes, hipMemcpyDeviceToDevice, st));
-        VL_HIP(hipMemcpyAsync(aws + A.w, grad_final_dev, fbytes, hipMemcpyDeviceToDevice, st));
-        VL_HIP(hipMemsetAsync(aws + A.totals, 0, sizeof(double) * 9 * ctx->subs.size(), st));
-        std::vector<int> ob(ctx->n_sims + 1, 0);
-        for (int k = 0; k < ctx->n_sims; ++k) ob[k + 1] = ob[k] + ctx->sims[k].n_cells * ctx->sims[k].ns;
-        VL_HIP(hipMemcpyAsync(aws + A.out_base, ob.data(), sizeof(int) * ob.size(), hipMemcpyHostToDevice, st));
-        if (n_cells_sub > 0) {
-            VL_HIP(hipMemsetAsync(dS_dev, 0, sizeof(double) * n_cells_sub, st));
-            VL_HIP(hipMemsetAsync(dU_dev, 0, sizeof(double) * n_cells_sub, st));
-        }
-        int total_occ = 0;
-        for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
-        const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
-        const float2 *coef = ctx->at<float2>(ctx->o_coef32);
-        float *w = (float *)(aws + A.w);
-        for (int seg = A.nseg - 1; seg >= 0 && n_steps > 0; --seg) {
-            const int t0 = seg * K, t1 = std::min(t0 + K, n_steps);
-            VL_HIP(hipMemcpyAsync(ctx->field, aws + A.ck + F * seg, fbytes, hipMemcpyDeviceToDevice, st));
-            for (int t = t0; t < t1; ++t) {
-                VL_HIP(hipMemcpyAsync(aws + A.seg + F * (t - t0), ctx->field, fbytes, hipMemcpyDeviceToDevice, st));
-                if (t + 1 < t1)
-                    if (int r = enqueue_step(ctx)) return r;
-            }
-            for (int t = t1 - 1; t >= t0; --t) {
-                VL_HIP(hipMemcpyAsync(ctx->field, aws + A.seg + F * (t - t0), fbytes, hipMemcpyDeviceToDevice, st));
-                if (int r = replay_step(ctx, aws, A)) return r;
-                VL_HIP(vl::launch_sources_adjoint(
-                    ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims, ctx->at<int>(ctx->o_occ_prefix), total_occ,
-                    ctx->max_ns, subs, ctx->at<int>(ctx->o_occ_vox_v), ctx->at<int>(ctx->o_seg_start),
-                    ctx->at<double2>(ctx->o_ab), ctx->at<double>(ctx->o_krs), ctx->at<double>(ctx->o_kcell),
-                    ctx->at<int>(ctx->o_cell_of), (const float *)(aws + A.r8), w, (const int *)(aws + A.out_base),
-                    dS_dev, dU_dev, st));
-                for (int axis = 2; axis >= 0; --axis)
-                    for (const Launch &L : ctx->launches) {
-                        if (L.axis != axis) continue;
-                        vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
-                                          ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles, 0};
-                        VL_HIP(vl::launch_adjoint_sweep(axis, L.cap_idx, d, subs, coef, w,
-                                                        (const float *)(aws + A.raw[axis]),
-                                                        (double *)(aws + A.part), st));
-                        VL_HIP(vl::launch_reduce_partials(d, axis, (const double *)(aws + A.part),
-                                                          (double *)(aws + A.totals), st));
-                    }
-            }
-        }
-        if (grad_rho0_dev)
-            VL_HIP(hipMemcpyAsync(grad_rho0_dev, w, fbytes, hipMemcpyDeviceToDevice, st));
-        VL_HIP(hipMemcpyAsync(ctx->field, aws + A.ck, fbytes, hipMemcpyDeviceToDevice, st));
-        std::vector<double> T(9 * ctx->subs.size());
-        VL_HIP(hipMemcpyAsync(T.data(), aws + A.totals, sizeof(double) * T.size(), hipMemcpyDeviceToHost, st));
-        VL_HIP(hipStreamSynchronize(st));
-        for (size_t q = 0; q < ctx->subs.size(); ++q) {
-            const SubDev &d = ctx->subs[q];
-            const SimHost &s = ctx->sims[d.sim];
-            const double fx = d.fdec;  // folded into the x solve's table
-            double gd = 0.0, gl = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                const double gc = T[3 * (3 * q + a) + 0] / (a == 0 ? fx : 1.0);
-                gd += gc * ctx->dt / (s.h[a] * s.h[a]);
-                if (ctx->decay == VL_DECAY_THIRDS) gl += T[3 * (3 * q + a) + 1] * ctx->dt / 3.0;
-            }
-            if (ctx->decay == VL_DECAY_ONCE) gl = -ctx->dt * fx * T[3 * (3 * q + 0) + 2];
-            if (dD) dD[q] = gd;
-            if (dlambda) dlambda[q] = gl;
-        }
-        return VL_OK;
+    auto copy = [&](void *dst, const void *src) {
+        return timed(ctx, VL_K_ADJ_COPY, [&] { return hipMemcpyAsync(dst, src, fbytes, hipMemcpyDeviceToDevice, st); });
     };
-    rc = run();
-    ctx->profiling = was_profiling;
-    return rc;
+    // bounded number of pending event pairs while profiling
+    auto drain = [&]() { return ctx->recs.size() > 200000 ? collect_events(ctx) : VL_OK; };
+
+    // forward with checkpoints
+    for (int t = 0; t < n_steps; ++t) {
+        if (t % K == 0)
+            if (int r = copy(aws + A.ck + F * (t / K), ctx->field)) return r;
+        if (int r = enqueue_step(ctx)) return r;
+        if (int r = drain()) return r;
+    }
+    if (n_steps == 0)
+        if (int r = copy(aws + A.ck, ctx->field)) return r;
+    if (int r = copy(aws + A.w, grad_final_dev)) return r;
+    VL_HIP(hipMemsetAsync(aws + A.totals, 0, sizeof(double) * 9 * ctx->subs.size(), st));
+    if (A.n_slots) VL_HIP(hipMemsetAsync(aws + A.part, 0, sizeof(double) * A.n_slots, st));
+    std::vector<int> ob(ctx->n_sims + 1, 0);
+    for (int k = 0; k < ctx->n_sims; ++k) ob[k + 1] = ob[k] + ctx->sims[k].n_cells * ctx->sims[k].ns;
+    VL_HIP(hipMemcpyAsync(aws + A.out_base, ob.data(), sizeof(int) * ob.size(), hipMemcpyHostToDevice, st));
+    if (n_cells_sub > 0) {
+        VL_HIP(hipMemsetAsync(dS_dev, 0, sizeof(double) * n_cells_sub, st));
+        VL_HIP(hipMemsetAsync(dU_dev, 0, sizeof(double) * n_cells_sub, st));
+    }
+    int total_occ = 0;
+    for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+    const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
+    const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+    float *w = (float *)(aws + A.w);
+    for (int seg = A.nseg - 1; seg >= 0 && n_steps > 0; --seg) {
+        const int t0 = seg * K, t1 = std::min(t0 + K, n_steps);
+        if (int r = copy(ctx->field, aws + A.ck + F * seg)) return r;
+        for (int t = t0; t < t1; ++t) {
+            if (int r = copy(aws + A.seg + F * (t - t0), ctx->field)) return r;
+            if (t + 1 < t1)
+                if (int r = enqueue_step(ctx)) return r;
+        }
+        for (int t = t1 - 1; t >= t0; --t) {
+            if (int r = copy(ctx->field, aws + A.seg + F * (t - t0))) return r;
+            if (int r = replay_step(ctx, aws, A)) return r;
+            if (int r = timed(ctx, VL_K_ADJ_SOURCES, [&] {
+                    return vl::launch_sources_adjoint(
+                        ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims, ctx->at<int>(ctx->o_occ_prefix), total_occ,
+                        ctx->max_ns, subs, ctx->at<int>(ctx->o_occ_vox_v), ctx->at<int>(ctx->o_seg_start),
+                        ctx->at<double2>(ctx->o_ab), ctx->at<double>(ctx->o_krs), ctx->at<double>(ctx->o_kcell),
+                        ctx->at<int>(ctx->o_cell_of), (const float *)ctx->field, w,
+                        (const int *)(aws + A.out_base), dS_dev, dU_dev, st);
+                }))
+                return r;
+            for (int axis = 2; axis >= 0; --axis)
+                for (size_t li = 0; li < ctx->launches.size(); ++li) {
+                    const Launch &L = ctx->launches[li];
+                    if (L.axis != axis) continue;
+                    vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
+                                      ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles, 0};
+                    if (int r = timed(ctx, VL_K_ADJ_X + axis, [&] {
+                            return vl::launch_adjoint_sweep(axis, L.cap_idx, d, subs, coef, w,
+                                                            (const float *)(aws + A.raw[axis]),
+                                                            (double *)(aws + A.part) + A.part_off[li], st);
+                        }))
+                        return r;
+                }
+            if (int r = drain()) return r;
+        }
+    }
+    // each tile summed its own contributions over all steps; add the tiles
+    // of every volume in tile order
+    for (size_t li = 0; li < ctx->launches.size(); ++li) {
+        const Launch &L = ctx->launches[li];
+        vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
+                          L.count, L.total_tiles, 0};
+        if (int r = timed(ctx, VL_K_ADJ_REDUCE, [&] {
+                return vl::launch_reduce_partials(d, L.axis, (const double *)(aws + A.part) + A.part_off[li],
+                                                  (double *)(aws + A.totals), st);
+            }))
+            return r;
+    }
+    if (grad_rho0_dev)
+        if (int r = copy(grad_rho0_dev, w)) return r;
+    if (int r = copy(ctx->field, aws + A.ck)) return r;
+    std::vector<double> T(9 * ctx->subs.size());
+    VL_HIP(hipMemcpyAsync(T.data(), aws + A.totals, sizeof(double) * T.size(), hipMemcpyDeviceToHost, st));
+    VL_HIP(hipStreamSynchronize(st));
+    for (size_t q = 0; q < ctx->subs.size(); ++q) {
+        const SubDev &d = ctx->subs[q];
+        const SimHost &s = ctx->sims[d.sim];
+        const double fx = d.fdec;  // folded into the x solve's table
+        double gd = 0.0, gl = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double gc = T[3 * (3 * q + a) + 0] / (a == 0 ? fx : 1.0);
+            gd += gc * ctx->dt / (s.h[a] * s.h[a]);
+            if (ctx->decay == VL_DECAY_THIRDS) gl += T[3 * (3 * q + a) + 1] * ctx->dt / 3.0;
+        }
+        if (ctx->decay == VL_DECAY_ONCE) gl = -ctx->dt * fx * T[3 * (3 * q + 0) + 2];
+        if (dD) dD[q] = gd;
+        if (dlambda) dlambda[q] = gl;
+    }
+    return VL_OK;
 }
 
 }  // extern "C"

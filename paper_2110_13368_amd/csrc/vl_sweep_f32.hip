@@ -201,11 +201,32 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     if (raw != nullptr) {
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw + base, S.base + S.vol - base);
         if (AXIS == 0) {
-            // each lane along its own x-line: uncoalesced, used only when replaying
+            // through the LDS stage, like the field store below
+            float *st = stage + wave * 64 * 65;
             if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm);
-            const int col0 = top ? 0 : (n - 1) * 4;
-            const int cstep = top ? 4 : -4;
-            VL_FOR_UP(CAP, nel, t, bstore(rr, lane_b, col0 + t * cstep, v[t]);)
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                if (c * 64 < nel) {
+                    if (top) {
+#pragma unroll
+                        for (int jj = 0; jj < 64; ++jj)
+                            if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + jj] = v[c * 64 + jj];
+                    } else {
+#pragma unroll
+                        for (int jj = 0; jj < 64; ++jj)
+                            if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + 63 - jj] = v[c * 64 + jj];
+                    }
+                    wave_sync_lds();
+                    const int cs = top ? c * 64 : n - 64 * (c + 1);
+                    const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
+                    const int so = col - cs;
+                    const unsigned cb4 = (unsigned)col * 4u;
+#pragma unroll 16
+                    for (int q = 0; q < 64; ++q)
+                        if (q < xrows_left) bstore(rr, cb4, q * row_b, st[q * 65 + so]);
+                    wave_sync_lds();
+                }
+            }
         } else {
             if (top) bstore(rr, lane_b, m * row_b, xm);
             const int row0 = top ? 0 : (n - 1) * row_b;
