@@ -71,6 +71,11 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
 }
+typedef unsigned vl_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float4 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(vl_u32x4, v), r, (int)voff, soff, 0);
+}
 
 // Runs BODY for t = 0..CAP-1 with t < cnt, cnt wave-uniform: whole groups
 // of 8 without per-element tests.  Written as macros so that every register
@@ -111,13 +116,130 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
         }                                                                              \
     }
 
-// LDS of one tile.  The x sweep needs the 64x65 staging block per wave; the
-// others only the exchange slots and the pivot table.
+// LDS of one tile.  The x sweep needs a 64x64 staging block per wave (rows
+// padded to 65 floats, or 16 blocks of 4 rows padded to 260 floats: the same
+// size); the others only the exchange slots and the pivot table.
 template <int CAP, bool XSTAGE>
 struct TileLds {
     float xch[2][kWave];
     float2 piv[CAP];
-    float stage[XSTAGE ? 2 * 64 * 65 : 1];
+    __attribute__((aligned(16))) float stage[XSTAGE ? 2 * 64 * 65 : 1];
 };
+
+// ---------------------------------------------------------------------------
+// x lines with 16-byte transfers (long lines, CAP >= 160).  A 64-row x
+// 64-column chunk of the tile moves with 16 LDS-DMA instructions of 1 KB
+// (lane i: row 4k + i/16, one group of 4 columns) and 16 stores of 1 KB.
+// In the stage, block k holds rows 4k..4k+3 (64 floats each, block stride
+// 260 floats); row q's column group g sits in 16-byte slot (g + 4(q%4)) % 16.
+// With that rotation a lane's 16-byte read of 4 columns of its own row hits
+// distinct banks across any 16 consecutive lanes, and the DMA / store side
+// moves contiguous 16-byte slots.  Fewer VGPRs than the 4-byte path, so the
+// long-line classes run two waves per SIMD.
+constexpr int kXBlk = 260;
+template <int CAP>
+struct XWide {
+    static constexpr bool value = CAP >= 160;
+};
+
+// Loads this wave's half lines into v (top: columns 0..nel-1 in order; bottom:
+// columns n-1 downwards).  For CAP >= 64 every needed chunk starts at a
+// column >= 0 and ends at <= n-1, so only the top wave's unneeded groups past
+// n-4 are clamped.
+template <int CAP>
+__device__ __forceinline__ void x_load_wide(float (&v)[CAP], __amdgpu_buffer_rsrc_t rs, float *stw, bool top,
+                                            int n, int nel, int row_b, int xrows_left, int lane)
+{
+    constexpr int kChunks = (CAP + 63) / 64;
+    const int rb = lane >> 4;
+    const int gq = ((lane & 15) - 4 * rb) & 15;
+    const float *rowp = stw + (lane >> 2) * kXBlk + (lane & 3) * 64;
+    const int rot = 4 * (lane & 3);
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        if (c * 64 < nel) {
+            const int cbase = top ? c * 64 : n - 64 * (c + 1);
+            const int col = top ? min(cbase + 4 * gq, n - 4) : cbase + 4 * gq;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void *)(stw + k * kXBlk), 16,
+                    min(4 * k + rb, xrows_left - 1) * row_b + col * 4, 0, 0, 0);
+            __builtin_amdgcn_s_waitcnt(0);
+            wave_sync_lds();
+#pragma unroll
+            for (int h = 0; h < 16; ++h) {
+                if (c * 64 + 4 * h < CAP && c * 64 + 4 * h < nel) {
+                    const int gh = top ? h : 15 - h;
+                    const float4 q4 = *reinterpret_cast<const float4 *>(rowp + 4 * ((gh + rot) & 15));
+                    const float e4[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (c * 64 + 4 * h + e < CAP) v[c * 64 + 4 * h + e] = top ? e4[e] : e4[3 - e];
+                }
+            }
+            wave_sync_lds();
+        }
+    }
+}
+
+// Stores this wave's half lines from v (the middle row is stored by the
+// caller).  Column groups wholly owned by the wave go out as 16-byte stores;
+// the one group per row that straddles the wave's first/last owned column is
+// written element by element by the lane that owns the row.
+template <int CAP>
+__device__ __forceinline__ void x_store_wide(const float (&v)[CAP], __amdgpu_buffer_rsrc_t rs, float *stw, bool top,
+                                             int n, int nel, int row_b, int xrows_left, int lane, unsigned lane_b,
+                                             bool line_ok)
+{
+    constexpr int kChunks = (CAP + 63) / 64;
+    const int rb = lane >> 4;
+    const int gq = ((lane & 15) - 4 * rb) & 15;
+    float *rowp = stw + (lane >> 2) * kXBlk + (lane & 3) * 64;
+    const int rot = 4 * (lane & 3);
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        if (c * 64 < nel) {
+#pragma unroll
+            for (int h = 0; h < 16; ++h) {
+                if (c * 64 + 4 * h < CAP && c * 64 + 4 * h < nel) {
+                    const int gh = top ? h : 15 - h;
+                    float e4[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int idx = c * 64 + 4 * h + (top ? e : 3 - e);
+                        e4[e] = (idx < CAP) ? v[idx < CAP ? idx : 0] : 0.f;
+                    }
+                    *reinterpret_cast<float4 *>(rowp + 4 * ((gh + rot) & 15)) =
+                        make_float4(e4[0], e4[1], e4[2], e4[3]);
+                }
+            }
+            wave_sync_lds();
+            const int own = nel - c * 64;  // columns of this chunk the wave owns
+            const int cbase = top ? c * 64 : n - 64 * (c + 1);
+            const bool full = top ? (4 * gq + 3 < own) : (4 * gq >= 64 - own);
+            const unsigned col4 = (unsigned)(cbase + 4 * gq) * 4u;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (full && 4 * k + rb < xrows_left)
+                    bstore4(rs, col4, (4 * k + rb) * row_b, *reinterpret_cast<const float4 *>(stw + k * kXBlk + 4 * lane));
+            if (own < 64) {
+                const int first = top ? 0 : 64 - own;  // owned chunk columns [first, last)
+                const int last = top ? own : 64;
+                const int gp = first == 0 ? (own >> 2) : (first >> 2);
+                const bool partial = top ? (own & 3) != 0 : (first & 3) != 0;
+                if (partial && line_ok) {
+                    const float *src = rowp + 4 * ((gp + rot) & 15);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int tc = 4 * gp + e;
+                        if (tc >= first && tc < last) bstore(rs, lane_b + (unsigned)(cbase + tc) * 4u, 0, src[e]);
+                    }
+                }
+            }
+            wave_sync_lds();
+        }
+    }
+}
 
 }  // namespace vl

@@ -72,10 +72,12 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     unsigned lane_b = 0;     // per-lane byte offset (y, z: along x; x: row start)
     int row_b = 0;           // bytes between rows (y, z) / between x-lines (x)
     int xrows_left = 0;      // x-lines of the tile that exist
+    bool line_ok = true;     // this lane's line exists (x: not a clamped copy)
     if (AXIS == 0) {
         const int nrows = ny * nz;
         const int r0 = local * kTileLines;
         const int r = min(r0 + lane, nrows - 1);
+        line_ok = r0 + lane < nrows;
         const int j = r % ny, k = r / ny;
         on = (j == 0 ? 1 << 2 : 0) | (j == ny - 1 ? 1 << 3 : 0) |
              (k == 0 ? 1 << 4 : 0) | (k == nz - 1 ? 1 << 5 : 0);
@@ -117,7 +119,9 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     float v[CAP];
 
     // ---- load the half line (local t: wave 0 row t, wave 1 row n-1-t) ----
-    if (AXIS == 0) {
+    if (AXIS == 0 && XWide<CAP>::value) {
+        x_load_wide<CAP>(v, rs, stage + wave * 64 * 65, top, n, nel, row_b, xrows_left, lane);
+    } else if (AXIS == 0) {
         float *st = stage + wave * 64 * 65;
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
@@ -200,7 +204,10 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     // ---- raw solve output before the Dirichlet projection (adjoint replay) ----
     if (raw != nullptr) {
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw + base, S.base + S.vol - base);
-        if (AXIS == 0) {
+        if (AXIS == 0 && XWide<CAP>::value) {
+            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm);
+            x_store_wide<CAP>(v, rr, stage + wave * 64 * 65, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
+        } else if (AXIS == 0) {
             // through the LDS stage, like the field store below
             float *st = stage + wave * 64 * 65;
             if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm);
@@ -255,7 +262,10 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     }
 
     // ---- store ----
-    if (AXIS == 0) {
+    if (AXIS == 0 && XWide<CAP>::value) {
+        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm);
+        x_store_wide<CAP>(v, rs, stage + wave * 64 * 65, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
+    } else if (AXIS == 0) {
         float *st = stage + wave * 64 * 65;
         if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm);
 #pragma unroll
