@@ -101,7 +101,8 @@ extern "C" {
 #define VL_K_ADJ_SOURCES 13
 #define VL_K_ADJ_REDUCE 14
 #define VL_K_ADJ_COPY 15 /* checkpoint and state copies */
-#define VL_K_COUNT 16
+#define VL_K_SWEEP_XY 16  /* x and y solves of one z-plane per workgroup */
+#define VL_K_COUNT 17
 
 typedef struct vl_ctx vl_ctx;
 
@@ -205,13 +206,23 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * with 1 each XCD gets a contiguous range of tiles (neighbouring tiles share
  * an L2), with 0 tiles follow the workgroup index. */
 #define VL_OPT_XCD_ORDER 5
+/* VL_OPT_FUSE_XY (FP32 path, default 0): 1 solves x and y of every z-plane
+ * that fits in LDS (160 KiB: about 200 x 200 voxels) in one workgroup, which
+ * reads and writes the field once for both solves; volumes with larger
+ * planes keep the separate x and y sweeps.  Fields are bitwise identical
+ * either way.  One plane per workgroup leaves its load, solve and store
+ * phases unoverlapped, so on the grids measured so far the separate sweeps
+ * are as fast or faster; vl_tune times both.  Without the device's support
+ * for that much LDS per workgroup the option has no effect. */
+#define VL_OPT_FUSE_XY 6
 /* Selecting VL_MODE_PERSISTENT currently fails with VL_E_STATE: the one-launch
  * step is switched off until a hang seen in its first GPU runs is explained. */
 int vl_set_option(vl_ctx *ctx, int option, int value);
 int vl_get_option(vl_ctx *ctx, int option, int *value);
 
-/* Autotuner: times the candidate launch configurations (XCD tile order on or
- * off, sources fused into the z sweep or separate) on the bound buffers, a
+/* Autotuner: times the candidate launch configurations (x+y per z-plane or
+ * separate sweeps, XCD tile order on or off, sources fused into the z sweep
+ * or separate) on the bound buffers, a
  * few steps each (which overwrite the field), and keeps the fastest.  With a
  * non-NULL cache_path the choice is read from / appended to that text file,
  * keyed by precision, decay split and every volume's shape, so a second call

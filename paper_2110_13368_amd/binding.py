@@ -28,10 +28,11 @@ VL_SOA, VL_AOS = 0, 1
 VL_OPT_FUSE_SOURCES, VL_OPT_STEP_MODE, VL_OPT_PERSISTENT_GRID, VL_OPT_WAIT_LIMIT_US = 1, 2, 3, 4
 VL_MODE_LAUNCHES, VL_MODE_PERSISTENT = 0, 1
 VL_OPT_XCD_ORDER = 5
+VL_OPT_FUSE_XY = 6
 VL_K_SWEEP_X, VL_K_SWEEP_Y, VL_K_SWEEP_Z, VL_K_SOURCES, VL_K_DIRICHLET, VL_K_DECAY, VL_K_STEP = range(7)
 KERNEL_NAMES = ["sweep_x", "sweep_y", "sweep_z", "sources", "dirichlet", "decay", "step",
                 "replay_x", "replay_y", "replay_z", "adjoint_x", "adjoint_y", "adjoint_z",
-                "adjoint_sources", "adjoint_reduce", "adjoint_copy"]
+                "adjoint_sources", "adjoint_reduce", "adjoint_copy", "sweep_xy"]
 
 # exported symbol -> (restype, argtypes)
 _vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t

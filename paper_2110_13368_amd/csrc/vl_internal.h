@@ -19,6 +19,20 @@ constexpr int kWave = 64;
 constexpr int kNumCaps = 7;
 constexpr int kCaps[kNumCaps] = {32, 64, 96, 128, 160, 200, 256};
 
+// x and y solves of one z-plane per workgroup (volumes whose plane fits in
+// LDS): four wave pairs; plane rows padded to an odd stride so that 64 lanes
+// walking 64 consecutive rows hit 64 different banks.
+constexpr int kXYThreads = 512;
+constexpr size_t kXYMaxLds = 160 * 1024;
+__host__ __device__ constexpr int xy_row_stride(int nx) { return nx | 1; }
+// dynamic LDS of that kernel: pivot tables of both axes, one exchange slot
+// per lane of each wave pair, the plane
+inline size_t xy_lds_bytes(int nx, int ny)
+{
+    const size_t cbx = (size_t)(nx - 1 - (nx - 1) / 2), cby = (size_t)(ny - 1 - (ny - 1) / 2);
+    return (cbx + cby) * 8 + (size_t)(kXYThreads / 2) * 4 + (size_t)ny * xy_row_stride(nx) * 4;
+}
+
 // One (simulation, substrate) volume.
 struct SubDev {
     long long base;      // element offset of voxel (0,0,0) in the field
@@ -89,6 +103,13 @@ struct StepQueue {
 // a1: coefficients.  One thread per (volume, axis), FP64 recurrences.
 hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
                                double2 *coef64, SubDev *subs_rw, hipStream_t st);
+
+// a3+a4 for volumes whose z-plane fits in LDS: x then y solve of one plane per
+// workgroup (tile_prefix counts planes); lds_bytes as from xy_lds_bytes.
+// prepare_sweep_xy raises the kernel's dynamic-LDS limit (once per device).
+hipError_t prepare_sweep_xy(size_t lds_bytes);
+hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev *subs, const float2 *coef,
+                           float *field, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
 // raw (may be null, same layout as the field) receives each solve's output

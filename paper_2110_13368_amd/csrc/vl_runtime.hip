@@ -61,8 +61,9 @@ struct SimHost {
 };
 
 struct Launch {
-    int axis, cap_idx, count, total_tiles;
+    int axis, cap_idx, count, total_tiles;  // axis 3: x and y of one z-plane per tile
     size_t ids_off, prefix_off;  // element offsets into the int table
+    size_t lds = 0;              // dynamic LDS bytes (axis 3)
 };
 
 struct Rec {
@@ -101,6 +102,12 @@ struct vl_ctx {
     int key_pad = 0;       // next_pow2(stage_cells)
     int zl_total = 0;      // sum over sims with cells of (nx*ny + 1)
     bool fuse_sources = true;
+    // x and y solved together per z-plane where the plane fits in LDS: the
+    // launches of that mode (planes, and x / y of the other volumes)
+    bool fuse_xy = false;
+    bool xy_ready = false;  // set at bind when the device takes xy_lds_max
+    std::vector<Launch> xy_launches;
+    size_t xy_lds_max = 0;
     bool xcd_order = true;
 
     // one-launch step (FP32): queue over all tiles of the three sweeps
@@ -264,17 +271,31 @@ int enqueue_step(vl_ctx *ctx)
             });
             if (rc) return rc;
         } else {
-        for (int axis = 0; axis < 3; ++axis)
-            for (const Launch &L : ctx->launches) {
-                if (L.axis != axis) continue;
-                vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
-                                  ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
-                                  ctx->xcd_order ? 1 : 0};
-                rc = timed(ctx, VL_K_SWEEP_X + axis, [&] {
-                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, nullptr, src, st);
-                });
-                if (rc) return rc;
+        const bool xy = ctx->fuse_xy && ctx->xy_ready;
+        auto sweep = [&](const Launch &L) -> int {
+            vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
+                              L.count, L.total_tiles, ctx->xcd_order ? 1 : 0};
+            if (L.axis == 3) {
+                d.xcd_order = 0;
+                return timed(ctx, VL_K_SWEEP_XY,
+                             [&] { return vl::launch_sweep_xy(d, L.lds, subs, coef, field, st); });
             }
+            return timed(ctx, VL_K_SWEEP_X + L.axis, [&] {
+                return vl::launch_sweep_f32(L.axis, L.cap_idx, d, subs, coef, field, nullptr, src, st);
+            });
+        };
+        for (int axis = 0; axis < 3; ++axis) {
+            if (xy && axis < 2) {
+                for (const Launch &L : ctx->xy_launches)
+                    if (L.axis == axis && (rc = sweep(L))) return rc;
+                if (axis == 1)
+                    for (const Launch &L : ctx->xy_launches)
+                        if (L.axis == 3 && (rc = sweep(L))) return rc;
+                continue;
+            }
+            for (const Launch &L : ctx->launches)
+                if (L.axis == axis && (rc = sweep(L))) return rc;
+        }
         }
         if (total_occ > 0 && !fused) {
             rc = timed(ctx, VL_K_SOURCES, [&] {
@@ -564,6 +585,71 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             }
         }
     }
+    // x+y per z-plane: volumes whose plane fits in LDS, grouped by LDS size
+    // so that small planes keep several workgroups per CU; the x and y
+    // launches of the other volumes as above
+    ctx->xy_launches.clear();
+    ctx->xy_lds_max = 0;
+    if (ctx->precision == VL_F32) {
+        std::vector<char> in_plane(nsubs, 0);
+        for (int q = 0; q < nsubs; ++q)
+            in_plane[q] = vl::xy_lds_bytes(ctx->subs[q].n[0], ctx->subs[q].n[1]) <= vl::kXYMaxLds;
+        for (int axis = 0; axis < 2; ++axis) {
+            std::vector<std::vector<int>> groups(vl::kNumCaps);
+            for (int q = 0; q < nsubs; ++q)
+                if (!in_plane[q]) groups[cap_index(ctx->subs[q].n[axis] - 1 - (ctx->subs[q].n[axis] - 1) / 2)].push_back(q);
+            for (int ci = 0; ci < vl::kNumCaps; ++ci) {
+                if (groups[ci].empty()) continue;
+                Launch L;
+                L.axis = axis;
+                L.cap_idx = ci;
+                L.count = (int)groups[ci].size();
+                L.ids_off = ctx->itable.size();
+                for (int q : groups[ci]) ctx->itable.push_back(q);
+                L.prefix_off = ctx->itable.size();
+                long long acc = 0;
+                for (int q : groups[ci]) {
+                    ctx->itable.push_back((int)acc);
+                    const SubDev &d = ctx->subs[q];
+                    acc += (d.vol / d.n[axis] + vl::kTileLines - 1) / vl::kTileLines;
+                }
+                ctx->itable.push_back((int)acc);
+                L.total_tiles = (int)acc;
+                ctx->xy_launches.push_back(L);
+            }
+        }
+        const size_t lds_class[3] = {40 * 1024, 80 * 1024, vl::kXYMaxLds};
+        for (int c = 0; c < 3; ++c) {
+            std::vector<int> ids;
+            size_t lds = 0;
+            for (int q = 0; q < nsubs; ++q) {
+                if (!in_plane[q]) continue;
+                const size_t b = vl::xy_lds_bytes(ctx->subs[q].n[0], ctx->subs[q].n[1]);
+                if (b <= lds_class[c] && (c == 0 || b > lds_class[c - 1])) {
+                    ids.push_back(q);
+                    lds = std::max(lds, b);
+                }
+            }
+            if (ids.empty()) continue;
+            Launch L;
+            L.axis = 3;
+            L.cap_idx = 0;
+            L.count = (int)ids.size();
+            L.lds = lds;
+            L.ids_off = ctx->itable.size();
+            for (int q : ids) ctx->itable.push_back(q);
+            L.prefix_off = ctx->itable.size();
+            long long acc = 0;
+            for (int q : ids) {
+                ctx->itable.push_back((int)acc);
+                acc += ctx->subs[q].n[2];
+            }
+            ctx->itable.push_back((int)acc);
+            L.total_tiles = (int)acc;
+            ctx->xy_launches.push_back(L);
+            ctx->xy_lds_max = std::max(ctx->xy_lds_max, lds);
+        }
+    }
     // one-launch step: every volume, tiles of x, then y, then z in one queue
     ctx->queue_cap_idx = 0;
     ctx->queue_total = 0;
@@ -741,6 +827,12 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
         s.n_occ = 0;
         s.n_out = 0;
     }
+    // the x+y plane kernel needs more than the default dynamic-LDS limit;
+    // without it the separate x and y sweeps run
+    ctx->xy_ready = false;
+    if (ctx->xy_lds_max > 0)
+        ctx->xy_ready = vl::prepare_sweep_xy(ctx->xy_lds_max) == hipSuccess;
+    (void)hipGetLastError();
     ctx->bound = true;
     if (int rc = upload_cell_tables(ctx)) return rc;
     VL_HIP(hipStreamSynchronize(st));
@@ -1037,6 +1129,12 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         ctx->persistent_grid = value;
         return VL_OK;
     }
+    if (option == VL_OPT_FUSE_XY) {
+        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_FUSE_XY takes 0 or 1");
+        if (ctx->fuse_xy != (value == 1)) drop_graph(ctx);
+        ctx->fuse_xy = value == 1;
+        return VL_OK;
+    }
     if (option == VL_OPT_XCD_ORDER) {
         if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_XCD_ORDER takes 0 or 1");
         if (ctx->xcd_order != (value == 1)) drop_graph(ctx);
@@ -1062,6 +1160,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     case VL_OPT_PERSISTENT_GRID: *value = ctx->persistent_grid; return VL_OK;
     case VL_OPT_WAIT_LIMIT_US: *value = ctx->wait_limit_us; return VL_OK;
     case VL_OPT_XCD_ORDER: *value = ctx->xcd_order ? 1 : 0; return VL_OK;
+    case VL_OPT_FUSE_XY: *value = ctx->fuse_xy ? 1 : 0; return VL_OK;
     default: return fail(VL_E_ARG, "unknown option");
     }
 }
@@ -1095,22 +1194,24 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (ctx->precision != VL_F32) return VL_OK;  // the plain path has one shape
     const std::string key = tune_key(ctx);
-    // a candidate: step mode, its grid, XCD-ordered tiles, fused sources
+    // a candidate: step mode, its grid, XCD-ordered tiles, fused sources,
+    // x+y per z-plane
     struct Cand {
-        int mode, grid, xcd, fuse;
+        int mode, grid, xcd, fuse, xy;
     };
     auto apply = [&](const Cand &c) -> int {
         if (int rc = vl_set_option(ctx, VL_OPT_STEP_MODE, c.mode)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_PERSISTENT_GRID, c.grid)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_XCD_ORDER, c.xcd)) return rc;
+        if (int rc = vl_set_option(ctx, VL_OPT_FUSE_XY, c.xy)) return rc;
         return vl_set_option(ctx, VL_OPT_FUSE_SOURCES, c.fuse);
     };
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "r")) {
             char k[128];
-            Cand c{0, 0, 1, 1};
+            Cand c{0, 0, 1, 1, 1};
             bool hit = false;
-            while (std::fscanf(f, "%127s %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse) == 5)
+            while (std::fscanf(f, "%127s %d %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse, &c.xy) == 6)
                 if (key == k) {
                     hit = true;
                     break;
@@ -1120,15 +1221,17 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
         }
     }
     std::vector<Cand> cands;
-    for (int xcd = 1; xcd >= 0; --xcd)
-        for (int fuse = 1; fuse >= 0; --fuse) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse});
+    const bool any_plane = ctx->xy_ready;
+    for (int xy = any_plane ? 1 : 0; xy >= 0; --xy)
+        for (int xcd = 1; xcd >= 0; --xcd)
+            for (int fuse = 1; fuse >= 0; --fuse) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy});
     if (one_launch_enabled()) {
         int per_cu = 1, cus = 1, dev = 0;
         VL_HIP(hipGetDevice(&dev));
         VL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         VL_HIP(vl::persistent_blocks_per_cu(ctx->queue_cap_idx, &per_cu));
         per_cu = std::max(per_cu, 1);
-        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1});
+        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1, 0});
     }
     const bool was_profiling = ctx->profiling;
     ctx->profiling = false;
@@ -1169,7 +1272,7 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     if ((rc = apply(pick))) return rc;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse);
+            std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse, pick.xy);
             std::fclose(f);
         }
     }

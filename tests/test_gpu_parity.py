@@ -197,16 +197,19 @@ def test_tuner_picks_a_mode_and_caches(tmp_path):
         xcd = ctx.get_option(vb.VL_OPT_XCD_ORDER)
         fuse = ctx.get_option(vb.VL_OPT_FUSE_SOURCES)
         assert ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_LAUNCHES
+        fxy = ctx.get_option(vb.VL_OPT_FUSE_XY)
         words = open(cache).read().split()
-        assert len(words) == 5 and int(words[3]) == xcd and int(words[4]) == fuse
+        assert len(words) == 6 and int(words[3]) == xcd and int(words[4]) == fuse and int(words[5]) == fxy
         # a second context with the same shapes reads the choice back
         ctx2 = vb.Context(wl.sims)
         ctx2.set_option(vb.VL_OPT_XCD_ORDER, 1 - xcd)
         ctx2.set_option(vb.VL_OPT_FUSE_SOURCES, 1 - fuse)
+        ctx2.set_option(vb.VL_OPT_FUSE_XY, 1 - fxy)
         ctx2.tune(cache)
         assert ctx2.get_option(vb.VL_OPT_XCD_ORDER) == xcd
         assert ctx2.get_option(vb.VL_OPT_FUSE_SOURCES) == fuse
-        assert len(open(cache).read().split()) == 5
+        assert ctx2.get_option(vb.VL_OPT_FUSE_XY) == fxy
+        assert len(open(cache).read().split()) == 6
         # the tuned context still computes the step correctly
         for k, s in enumerate(wl.sims):
             ctx2.set_field(k, s.rho0)
@@ -322,3 +325,45 @@ def test_full_batched_sampled():
     sizes = [int(np.prod(s.shape)) for s in wl.sims]
     for k in (int(np.argmin(sizes)), int(np.argmax(sizes)), 17):
         assert_close(fields[k], run_oracle(wl.sims[k], 3), 1e-5, f"batch sim {k} {wl.sims[k].shape}")
+
+
+# --------------------------------------------------------------------------
+# x and y of one z-plane per workgroup (planes that fit in LDS) against the
+# separate x and y sweeps: the same operations, so bitwise the same field.
+
+def _run_xy(specs, steps, fuse_xy, decay=vb.VL_DECAY_ONCE):
+    ctx = vb.Context(specs, decay_split=decay, device="cuda:0")
+    try:
+        ctx.set_option(vb.VL_OPT_FUSE_XY, fuse_xy)
+        ctx.set_profiling(True)
+        ctx.step(steps)
+        ctx.sync()
+        stats = ctx.kernel_stats()
+        return [ctx.get_field(k) for k in range(len(specs))], stats
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("decay", [vb.VL_DECAY_ONCE, vb.VL_DECAY_THIRDS])
+@pytest.mark.parametrize("shape,bc", [((200, 200, 5), "mixed"), ((199, 57, 9), "dirichlet"), ((64, 130, 6), "mixed"),
+                                      ((1, 40, 7), "mixed"), ((45, 1, 3), "dirichlet"), ((3, 2, 4), "mixed"),
+                                      ((2, 3, 1), "dirichlet"), ((129, 65, 2), "neumann")])
+def test_xy_plane_kernel_equals_separate_sweeps(shape, bc, decay):
+    spec = _spec(shape, 2, bc, 300, "f32", 71 + shape[0])
+    a, sa = _run_xy([spec], 3, 1, decay)
+    b, sb = _run_xy([spec], 3, 0, decay)
+    print(f"{shape} {bc}: plane launches {sa['sweep_xy'][0]}, separate x {sb['sweep_x'][0]}", flush=True)
+    assert sa["sweep_xy"][0] == 3 and sa["sweep_x"][0] == 0 and sb["sweep_xy"][0] == 0
+    assert np.array_equal(a[0], b[0])
+
+
+def test_xy_plane_kernel_mixed_batch():
+    # planes that fit (several LDS classes) next to one that does not
+    specs = [_spec(sh, 1 + k % 2, "mixed", 200, "f32", 90 + k)
+             for k, sh in enumerate([(30, 20, 5), (120, 100, 4), (201, 199, 3), (260, 210, 2), (7, 90, 6)])]
+    a, sa = _run_xy(specs, 2, 1)
+    b, _ = _run_xy(specs, 2, 0)
+    assert sa["sweep_xy"][0] > 0 and sa["sweep_x"][0] > 0  # the 260 x 210 plane keeps x and y
+    for k in range(len(specs)):
+        assert np.array_equal(a[k], b[k]), k
+    assert_close(a[2].astype(np.float64), run_oracle(specs[2], 2), 1e-5, "xy batch")
