@@ -17,6 +17,7 @@ a bounded sample of the same workload on the host's cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,6 +34,35 @@ UNIT = "voxel-substrate updates/s"
 
 
 LDS_PER_WORKGROUP = 160 * 1024  # gfx950
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mi355x.json")
+
+
+def source_digest(files) -> str:
+    """sha256 over the named kernel sources (paper_2110_13368_amd/csrc)."""
+    h = hashlib.sha256()
+    for name in sorted(files):
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2110_13368_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE /
+    WRITE_SIZE measurements (scaled by the copy-kernel calibration), or None
+    when there is none for this workload or the kernel's sources changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for e in table.get("entries", []):
+        if e.get("workload") == workload and e.get("kernel") == kernel:
+            if e.get("sources_sha256") != source_digest(e.get("sources", [])):
+                return None
+            return int(e["bytes_read"] + e["bytes_written"])
+    return None
 
 
 def plane_fits(nx: int, ny: int) -> bool:
@@ -263,6 +293,7 @@ def main():
                        vb.VL_MODE_PERSISTENT if args.mode == "persistent" else vb.VL_MODE_LAUNCHES)
     mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
     fuse_src = bool(ctx.get_option(vb.VL_OPT_FUSE_SOURCES))
+    xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))
     for k, s in enumerate(wl.sims):
         ctx.set_field(k, s.rho0)
     elapsed = time_steps(ctx, args.steps, args.warmup)
@@ -299,7 +330,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(alg_bytes / (per_step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if alg_bytes else None,
-        "traffic": None,
+        "traffic": measured_traffic(wl.name, dom),
         "avg_ms": round(per_step_ms / launches_per_step, 5),
         "launches_per_step": launches_per_step,
         "bytes_per_launch": alg_bytes / launches_per_step if alg_bytes else None,
@@ -337,7 +368,7 @@ def main():
                    "grid": list(wl.sims[0].shape) if len(wl.sims) == 1 else "ragged",
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
                    "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode,
-                   "xy_per_plane": fused_xy, "fuse_sources": fuse_src},
+                   "xy_per_plane": fused_xy, "fuse_sources": fuse_src, "xcd_order": xcd_ord},
         "hbm_effective": {"basis": "B_alg: three sweeps x (read + write) per voxel-substrate-step; with x and y "
                                    "solved per z-plane the step moves less than B_alg",
                           "bytes_per_update": b_alg,
