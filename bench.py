@@ -294,6 +294,7 @@ def main():
     mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
     fuse_src = bool(ctx.get_option(vb.VL_OPT_FUSE_SOURCES))
     xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))
+    x_lanes = bool(ctx.get_option(vb.VL_OPT_X_LANES)) if precision == vb.VL_F32 else False
     for k, s in enumerate(wl.sims):
         ctx.set_field(k, s.rho0)
     elapsed = time_steps(ctx, args.steps, args.warmup)
@@ -368,7 +369,8 @@ def main():
                    "grid": list(wl.sims[0].shape) if len(wl.sims) == 1 else "ragged",
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
                    "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode,
-                   "xy_per_plane": fused_xy, "fuse_sources": fuse_src, "xcd_order": xcd_ord},
+                   "xy_per_plane": fused_xy, "fuse_sources": fuse_src, "xcd_order": xcd_ord,
+                   "x_lanes_along_line": x_lanes},
         "hbm_effective": {"basis": "B_alg: three sweeps x (read + write) per voxel-substrate-step; with x and y "
                                    "solved per z-plane the step moves less than B_alg",
                           "bytes_per_update": b_alg,

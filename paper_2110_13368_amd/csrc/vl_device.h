@@ -72,6 +72,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
 }
 typedef unsigned vl_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned vl_u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float4 v)
 {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(vl_u32x4, v), r, (int)voff, soff, 0);

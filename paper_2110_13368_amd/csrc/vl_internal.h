@@ -49,8 +49,27 @@ struct SubDev {
     double c[3];         // dt*D/h_a^2 per axis
     double sigma;        // diagonal shift lambda*dt/3 (decay split over the solves) or 0
     double fdec;         // decay factor 1/(1 + lambda*dt) applied after the x solve, or 1
-    int pad_[2];
+    int xlane;           // first float of the lanes-along-the-line x table (FP32 path)
+    int pad_;
 };
+
+// x solve with lanes along the line (FP32 path, option): lane l of a wave
+// holds K = ceil(nx/64) consecutive voxels of one x-line.  The last voxel of
+// each lane's run is a separator; the voxels before it (the lane's interval)
+// are eliminated locally, the separators form a tridiagonal system over the
+// lanes whose matrix does not depend on the data, solved by parallel cyclic
+// reduction with precomputed multipliers.  Per volume a table of
+// xl_fields(K) rows of 64 floats (row-major by field, one column per lane):
+//   inv[t], e[t]     t < K-1   interval pivots (1/d_t, c/d_t)
+//   al[t], be[t]     t < K-1   interval response to the left / own separator
+//   k1[v], k2[v]     v < 6     multipliers of reduction level v (distance 2^v)
+//   binv                       1 / reduced diagonal after the last level
+//   cprev, cnext               c where the lane's / the next lane's interval
+//                              is not empty, else 0
+constexpr int kXLaneMaxK = 9;  // lines of up to 576 voxels
+constexpr int kXLaneLevels = 6;
+__host__ __device__ constexpr int xl_fields(int K) { return 4 * (K - 1) + 2 * kXLaneLevels + 3; }
+__host__ __device__ constexpr int xl_k(int n) { return n <= 64 ? 1 : (n + 63) / 64; }
 
 // One launch of an FP32 sweep over a group of volumes sharing a capacity
 // class: tiles of the listed volumes are numbered consecutively.
@@ -110,6 +129,14 @@ hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
 hipError_t prepare_sweep_xy(size_t lds_bytes);
 hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev *subs, const float2 *coef,
                            float *field, hipStream_t st);
+
+// a3 with lanes along the line: tables (one 64-thread workgroup per volume,
+// FP64 arithmetic) and the sweep for lines of K voxels per lane (tiles of 64
+// x-lines as for the split sweep).  raw as for launch_sweep_f32.
+hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *coef_unused, float *xl32,
+                            hipStream_t st);
+hipError_t launch_sweep_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
+                           float *raw, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
 // raw (may be null, same layout as the field) receives each solve's output

@@ -107,6 +107,11 @@ struct vl_ctx {
     bool fuse_xy = false;
     bool xy_ready = false;  // set at bind when the device takes xy_lds_max
     std::vector<Launch> xy_launches;
+    // x solve with lanes along the line: launches grouped by voxels per lane
+    // (cap_idx holds K) and the per-volume tables
+    bool x_lanes = false;
+    std::vector<Launch> xl_launches;
+    size_t n_xl32 = 0;
     size_t xy_lds_max = 0;
     bool xcd_order = true;
 
@@ -121,7 +126,7 @@ struct vl_ctx {
     int wait_limit_us = 2000000;  // a tile of the one-launch step waits at most this long
 
     // workspace layout (byte offsets)
-    size_t o_subs = 0, o_coef32 = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0;
+    size_t o_subs = 0, o_coef32 = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0, o_xl32 = 0;
     size_t o_cells = 0, o_occ_prefix = 0, o_occ_vox = 0, o_seg_start = 0, o_comp = 0, o_ab = 0;
     size_t o_pos = 0, o_V = 0, o_S = 0, o_U = 0, o_RS = 0, o_keys = 0, o_seg_id = 0;
     size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
@@ -285,6 +290,18 @@ int enqueue_step(vl_ctx *ctx)
             });
         };
         for (int axis = 0; axis < 3; ++axis) {
+            if (!xy && axis == 0 && ctx->x_lanes) {
+                for (const Launch &L : ctx->xl_launches) {
+                    vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
+                                      ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
+                                      ctx->xcd_order ? 1 : 0};
+                    rc = timed(ctx, VL_K_SWEEP_X, [&] {
+                        return vl::launch_sweep_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), field, nullptr, st);
+                    });
+                    if (rc) return rc;
+                }
+                continue;
+            }
             if (xy && axis < 2) {
                 for (const Launch &L : ctx->xy_launches)
                     if (L.axis == axis && (rc = sweep(L))) return rc;
@@ -507,7 +524,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     // field layout and volume descriptors
     ctx->subs.clear();
     size_t off = 0;
-    size_t c32 = 0, c64 = 0;
+    size_t c32 = 0, c64 = 0, xl = 0;
     ctx->max_ns = 0;
     for (int k = 0; k < ctx->n_sims; ++k) {
         SimHost &s = ctx->sims[k];
@@ -529,6 +546,11 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             }
             d.sim = k;
             d.sub = q;
+            d.xlane = -1;
+            if (ctx->precision == VL_F32 && s.n[0] <= 64 * vl::kXLaneMaxK) {
+                d.xlane = (int)xl;
+                xl += (size_t)vl::xl_fields(vl::xl_k(s.n[0])) * 64;
+            }
             set_rates(d, s, q, dt, ctx->decay);
             for (int f = 0; f < 6; ++f) {
                 if (s.bc_kind[(size_t)q * 6 + f] == VL_DIRICHLET) d.dir_mask |= 1 << f;
@@ -539,7 +561,9 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
         }
         off += (size_t)s.ns * s.vol_stride;
     }
-    if (c64 >= (1ull << 31) || c32 >= (1ull << 31)) return fail(VL_E_SHAPE, "too many coefficients");
+    if (c64 >= (1ull << 31) || c32 >= (1ull << 31) || xl >= (1ull << 31))
+        return fail(VL_E_SHAPE, "too many coefficients");
+    ctx->n_xl32 = std::max<size_t>(xl, 1);
     ctx->field_elems = off;
     ctx->n_coef32 = std::max<size_t>(c32, 1);
     ctx->n_coef64 = std::max<size_t>(c64, 1);
@@ -650,6 +674,32 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             ctx->xy_lds_max = std::max(ctx->xy_lds_max, lds);
         }
     }
+    // x with lanes along the line: volumes grouped by voxels per lane
+    ctx->xl_launches.clear();
+    if (ctx->precision == VL_F32) {
+        for (int K = 1; K <= vl::kXLaneMaxK; ++K) {
+            std::vector<int> ids;
+            for (int q = 0; q < nsubs; ++q)
+                if (ctx->subs[q].xlane >= 0 && vl::xl_k(ctx->subs[q].n[0]) == K) ids.push_back(q);
+            if (ids.empty()) continue;
+            Launch L;
+            L.axis = 0;
+            L.cap_idx = K;
+            L.count = (int)ids.size();
+            L.ids_off = ctx->itable.size();
+            for (int q : ids) ctx->itable.push_back(q);
+            L.prefix_off = ctx->itable.size();
+            long long acc = 0;
+            for (int q : ids) {
+                ctx->itable.push_back((int)acc);
+                const SubDev &d = ctx->subs[q];
+                acc += (d.vol / d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
+            }
+            ctx->itable.push_back((int)acc);
+            L.total_tiles = (int)acc;
+            ctx->xl_launches.push_back(L);
+        }
+    }
     // one-launch step: every volume, tiles of x, then y, then z in one queue
     ctx->queue_cap_idx = 0;
     ctx->queue_total = 0;
@@ -750,6 +800,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_subs = take(sizeof(SubDev) * nsubs);
     ctx->o_coef32 = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->n_coef32 : 0);
     ctx->o_coef64 = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->n_coef64 : 0);
+    ctx->o_xl32 = take(ctx->precision == VL_F32 ? sizeof(float) * ctx->n_xl32 : 0);
     ctx->o_itable = take(sizeof(int) * ctx->itable.size());
     ctx->o_lltable = take(sizeof(long long) * ctx->lltable.size());
     ctx->o_faces = take(sizeof(int4) * ctx->faces.size());
@@ -818,6 +869,9 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
                                    ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
                                    ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
                                    ctx->at<SubDev>(ctx->o_subs), st));
+    if (ctx->precision == VL_F32)
+        VL_HIP(vl::launch_xl_tables(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(), nullptr,
+                                    ctx->at<float>(ctx->o_xl32), st));
     if (ctx->zl_total > 0)
         VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_line_start, 0, sizeof(int) * ctx->zl_total, st));
     VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_qcounters, 0, sizeof(unsigned) * (2 + 3 * ctx->subs.size()), st));
@@ -860,6 +914,9 @@ int vl_update_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D, const
                                    ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
                                    ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
                                    ctx->at<SubDev>(ctx->o_subs), st));
+    if (ctx->precision == VL_F32)
+        VL_HIP(vl::launch_xl_tables(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(), nullptr,
+                                    ctx->at<float>(ctx->o_xl32), st));
     // the host copy of the descriptors must outlive the asynchronous upload
     VL_HIP(hipStreamSynchronize(st));
     return VL_OK;
@@ -1129,6 +1186,12 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         ctx->persistent_grid = value;
         return VL_OK;
     }
+    if (option == VL_OPT_X_LANES) {
+        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_X_LANES takes 0 or 1");
+        if (ctx->x_lanes != (value == 1)) drop_graph(ctx);
+        ctx->x_lanes = value == 1;
+        return VL_OK;
+    }
     if (option == VL_OPT_FUSE_XY) {
         if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_FUSE_XY takes 0 or 1");
         if (ctx->fuse_xy != (value == 1)) drop_graph(ctx);
@@ -1161,6 +1224,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     case VL_OPT_WAIT_LIMIT_US: *value = ctx->wait_limit_us; return VL_OK;
     case VL_OPT_XCD_ORDER: *value = ctx->xcd_order ? 1 : 0; return VL_OK;
     case VL_OPT_FUSE_XY: *value = ctx->fuse_xy ? 1 : 0; return VL_OK;
+    case VL_OPT_X_LANES: *value = ctx->x_lanes ? 1 : 0; return VL_OK;
     default: return fail(VL_E_ARG, "unknown option");
     }
 }
@@ -1197,21 +1261,22 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     // a candidate: step mode, its grid, XCD-ordered tiles, fused sources,
     // x+y per z-plane
     struct Cand {
-        int mode, grid, xcd, fuse, xy;
+        int mode, grid, xcd, fuse, xy, xl;
     };
     auto apply = [&](const Cand &c) -> int {
         if (int rc = vl_set_option(ctx, VL_OPT_STEP_MODE, c.mode)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_PERSISTENT_GRID, c.grid)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_XCD_ORDER, c.xcd)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_FUSE_XY, c.xy)) return rc;
+        if (int rc = vl_set_option(ctx, VL_OPT_X_LANES, c.xl)) return rc;
         return vl_set_option(ctx, VL_OPT_FUSE_SOURCES, c.fuse);
     };
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "r")) {
             char k[128];
-            Cand c{0, 0, 1, 1, 1};
+            Cand c{0, 0, 1, 1, 0, 0};
             bool hit = false;
-            while (std::fscanf(f, "%127s %d %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse, &c.xy) == 6)
+            while (std::fscanf(f, "%127s %d %d %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse, &c.xy, &c.xl) == 7)
                 if (key == k) {
                     hit = true;
                     break;
@@ -1223,15 +1288,16 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     std::vector<Cand> cands;
     const bool any_plane = ctx->xy_ready;
     for (int xy = any_plane ? 1 : 0; xy >= 0; --xy)
-        for (int xcd = 1; xcd >= 0; --xcd)
-            for (int fuse = 1; fuse >= 0; --fuse) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy});
+        for (int xl = xy ? 0 : 1; xl >= 0; --xl)
+            for (int xcd = 1; xcd >= 0; --xcd)
+                for (int fuse = 1; fuse >= 0; --fuse) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl});
     if (one_launch_enabled()) {
         int per_cu = 1, cus = 1, dev = 0;
         VL_HIP(hipGetDevice(&dev));
         VL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         VL_HIP(vl::persistent_blocks_per_cu(ctx->queue_cap_idx, &per_cu));
         per_cu = std::max(per_cu, 1);
-        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1, 0});
+        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1, 0, 0});
     }
     const bool was_profiling = ctx->profiling;
     ctx->profiling = false;
@@ -1272,7 +1338,8 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     if ((rc = apply(pick))) return rc;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse, pick.xy);
+            std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse, pick.xy,
+                         pick.xl);
             std::fclose(f);
         }
     }
@@ -1371,10 +1438,18 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
     const vl::FusedSources nosrc{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
                                  ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0};
     for (int axis = 0; axis < 3; ++axis)
-        for (const Launch &L : ctx->launches) {
+        for (const Launch &L : (axis == 0 && ctx->x_lanes) ? ctx->xl_launches : ctx->launches) {
             if (L.axis != axis) continue;
             vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
                               L.count, L.total_tiles, 1};
+            if (axis == 0 && ctx->x_lanes) {
+                if (int rc = timed(ctx, VL_K_REPLAY_X, [&] {
+                        return vl::launch_sweep_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), field,
+                                                   (float *)(aws + A.raw[0]), st);
+                    }))
+                    return rc;
+                continue;
+            }
             if (int rc = timed(ctx, VL_K_REPLAY_X + axis, [&] {
                     return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
                                                 nosrc, st);

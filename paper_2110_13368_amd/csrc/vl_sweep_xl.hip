@@ -1,0 +1,374 @@
+// vl_sweep_xl.hip -- the x solve with lanes along the line.
+//
+// x-lines are contiguous, so instead of transposing 64 lines through LDS (one
+// line per lane, as the split sweep does), lane l of a wave holds K =
+// ceil(nx/64) consecutive voxels of ONE line, loaded and stored with wide,
+// fully coalesced buffer instructions.  The line matrix T = tridiag(-c, b, -c)
+// is solved by substructuring:
+//   * the last voxel of each lane's run is a separator; the voxels before it
+//     form the lane's interval, eliminated locally (x_int = u + al*x_left +
+//     be*x_own, u = T_int^-1 r_int, al/be = T_int^-1 of the couplings c);
+//   * the separators satisfy a tridiagonal system over the lanes, A x_{l-1} +
+//     B x_l + C x_{l+1} = r_sep + c*u_last + c*u_first(next lane), whose matrix
+//     depends only on n, c and sigma: parallel cyclic reduction with
+//     precomputed multipliers solves it in six levels of two lane shuffles;
+//   * the intervals are completed from the separators.
+// The result equals the line solve up to rounding (it is the same linear
+// system; the order of operations differs from the split Thomas sweep).
+// Decay (once per step) multiplies the solution by f; the Dirichlet projection
+// before and after is applied as in the other sweeps.
+#include "vl_device.h"
+
+namespace vl {
+
+// ---------------------------------------------------------------------------
+// Tables, FP64 arithmetic: one workgroup of 64 threads per volume, thread l =
+// lane l.
+
+__device__ __forceinline__ double xl_bdiag(int n, int row, double c, double sg)
+{
+    if (n == 1) return 1.0 + sg;
+    return (row == 0 || row == n - 1) ? 1.0 + c + sg : 1.0 + 2.0 * c + sg;
+}
+
+__global__ void __launch_bounds__(64) xl_tables_kernel(const SubDev *__restrict__ subs, float *__restrict__ xl32)
+{
+    __shared__ double sa[64], sb[64], sc[64];
+    __shared__ double alf[64], ber[64];  // first al, first be of each lane's interval
+    __shared__ int mm[64];
+    const SubDev &S = subs[blockIdx.x];
+    const int l = threadIdx.x;
+    const int n = S.n[0];
+    if (S.xlane < 0) return;  // uniform per block
+    const int K = xl_k(n);
+    const int P = (n + K - 1) / K;
+    const double c = S.c[0], sg = S.sigma;
+    float *T = xl32 + S.xlane;
+    const int nf = xl_fields(K);
+    const bool act = l < P;
+    const int s0 = K * l;
+    const int e0 = act ? min(K * l + K - 1, n - 1) : 0;
+    const int m = act ? e0 - s0 : 0;
+
+    double inv[kXLaneMaxK - 1], ee[kXLaneMaxK - 1], al[kXLaneMaxK - 1], be[kXLaneMaxK - 1];
+    for (int t = 0; t < kXLaneMaxK - 1; ++t) inv[t] = ee[t] = al[t] = be[t] = 0.0;
+    double d = 0.0;
+    for (int t = 0; t < m; ++t) {
+        const double bt = xl_bdiag(n, s0 + t, c, sg);
+        d = (t == 0) ? bt : bt - c * c / d;
+        inv[t] = 1.0 / d;
+        ee[t] = c / d;
+    }
+    // responses of the interval to a unit coupling c at its first / last row
+    for (int pass = 0; pass < 2; ++pass) {
+        if (m == 0 || (pass == 0 && l == 0)) continue;  // lane 0's interval has no left separator
+        double y[kXLaneMaxK - 1];
+        double prev = 0.0;
+        for (int t = 0; t < m; ++t) {
+            const double rhs = (pass == 0 ? t == 0 : t == m - 1) ? c : 0.0;
+            prev = (rhs + c * prev) * inv[t];
+            y[t] = prev;
+        }
+        double nxt = 0.0;
+        for (int t = m - 1; t >= 0; --t) {
+            nxt = y[t] + ee[t] * nxt;
+            (pass == 0 ? al : be)[t] = nxt;
+        }
+    }
+    mm[l] = m;
+    alf[l] = al[0];
+    ber[l] = be[0];
+    __syncthreads();
+    // the reduced system of the separators
+    double A = 0.0, B = 1.0, C = 0.0;
+    if (act) {
+        const int mn = (l + 1 < P) ? mm[l + 1] : 0;
+        B = xl_bdiag(n, e0, c, sg);
+        if (e0 >= 1) {
+            if (m > 0) {
+                B -= c * be[m - 1];
+                A = (l > 0) ? -c * al[m - 1] : 0.0;
+            } else {
+                A = -c;  // the row before is the previous separator
+            }
+        }
+        if (e0 <= n - 2) {
+            if (mn > 0) {
+                B -= c * alf[l + 1];
+                C = -c * ber[l + 1];
+            } else {
+                C = -c;
+            }
+        }
+        T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + l] = (m > 0) ? (float)c : 0.f;   // cprev
+        T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + l] = (mn > 0) ? (float)c : 0.f;  // cnext
+    } else {
+        T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + l] = 0.f;
+        T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + l] = 0.f;
+    }
+    for (int t = 0; t < K - 1; ++t) {
+        T[(0 * (K - 1) + t) * 64 + l] = (float)inv[t];
+        T[(1 * (K - 1) + t) * 64 + l] = (float)ee[t];
+        T[(2 * (K - 1) + t) * 64 + l] = (float)al[t];
+        T[(3 * (K - 1) + t) * 64 + l] = (float)be[t];
+    }
+    // parallel cyclic reduction: level v eliminates the couplings at distance 2^v
+    sa[l] = A;
+    sb[l] = B;
+    sc[l] = C;
+    __syncthreads();
+    for (int v = 0; v < kXLaneLevels; ++v) {
+        const int s = 1 << v;
+        double k1 = 0.0, k2 = 0.0, na = 0.0, nb = sb[l], nc = 0.0;
+        if (act) {
+            if (l - s >= 0) {
+                k1 = sa[l] / sb[l - s];
+                na = -k1 * sa[l - s];
+                nb -= k1 * sc[l - s];
+            }
+            if (l + s < P) {
+                k2 = sc[l] / sb[l + s];
+                nc = -k2 * sc[l + s];
+                nb -= k2 * sa[l + s];
+            }
+        }
+        __syncthreads();
+        sa[l] = na;
+        sb[l] = nb;
+        sc[l] = nc;
+        T[(4 * (K - 1) + 2 * v) * 64 + l] = (float)k1;
+        T[(4 * (K - 1) + 2 * v + 1) * 64 + l] = (float)k2;
+        __syncthreads();
+    }
+    T[(4 * (K - 1) + 2 * kXLaneLevels) * 64 + l] = act ? (float)(1.0 / sb[l]) : 0.f;
+    (void)nf;
+}
+
+hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *, float *xl32, hipStream_t st)
+{
+    if (nsubs <= 0 || !xl32) return hipSuccess;
+    hipLaunchKernelGGL(xl_tables_kernel, dim3(nsubs), dim3(64), 0, st, subs, xl32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The sweep.  A workgroup of four waves takes one tile of 64 x-lines (the
+// split sweep's tiling); each wave solves 16 of them one after another, with
+// the next line's load issued before the current line is solved.
+
+template <int K>
+__device__ __forceinline__ void xl_load(float (&r)[K], __amdgpu_buffer_rsrc_t rs, unsigned voff)
+{
+    int t = 0;
+#pragma unroll
+    for (; t + 4 <= K; t += 4) {
+        const vl_u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(voff + 4u * t), 0, 0);
+        r[t] = __uint_as_float(q.x);
+        r[t + 1] = __uint_as_float(q.y);
+        r[t + 2] = __uint_as_float(q.z);
+        r[t + 3] = __uint_as_float(q.w);
+    }
+    if (t + 2 <= K) {
+        const vl_u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(voff + 4u * t), 0, 0);
+        r[t] = __uint_as_float(q.x);
+        r[t + 1] = __uint_as_float(q.y);
+        t += 2;
+    }
+    if (t < K) r[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(voff + 4u * t), 0, 0));
+}
+
+template <int K>
+__device__ __forceinline__ void xl_store(const float (&o)[K], __amdgpu_buffer_rsrc_t rs, unsigned voff, int cnt)
+{
+    if (cnt == K) {
+        int t = 0;
+#pragma unroll
+        for (; t + 4 <= K; t += 4)
+            __builtin_amdgcn_raw_buffer_store_b128(
+                vl_u32x4{__float_as_uint(o[t]), __float_as_uint(o[t + 1]), __float_as_uint(o[t + 2]),
+                         __float_as_uint(o[t + 3])},
+                rs, (int)(voff + 4u * t), 0, 0);
+        if (t + 2 <= K) {
+            __builtin_amdgcn_raw_buffer_store_b64(vl_u32x2{__float_as_uint(o[t]), __float_as_uint(o[t + 1])}, rs,
+                                                  (int)(voff + 4u * t), 0, 0);
+            t += 2;
+        }
+        if (t < K) bstore(rs, voff + 4u * t, 0, o[t]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+            if (t < cnt) bstore(rs, voff + 4u * t, 0, o[t]);
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict__ xl32,
+         float *__restrict__ field, float *__restrict__ raw)
+{
+    constexpr int KM = K > 1 ? K - 1 : 1;
+    const int tile = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int slot = find_slot(L.tile_prefix, L.count, tile);
+    const int local = tile - L.tile_prefix[slot];
+    const SubDev &S = subs[L.sub_ids[slot]];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int n = nx;
+    const int P = (n + K - 1) / K;
+    const bool act = lane < P;
+    const int m = act ? min(K * lane + K - 1, n - 1) - K * lane : 0;  // interval length
+    const int cnt = act ? m + 1 : 0;                                   // voxels of this lane
+    const int nrows = ny * nz;
+    const int row0 = local * kTileLines + wave * (kTileLines / 4);
+    const int dmask = S.dir_mask;
+    const int lo_f = (dmask & 1) ? 0 : -1;
+    const int hi_f = (dmask & 2) ? 1 : -1;
+    const float fdec = (float)S.fdec;
+
+    // this lane's table entries
+    const float *__restrict__ T = xl32 + S.xlane;
+    float inv[KM], ee[KM], al[KM], be[KM], k1[kXLaneLevels], k2[kXLaneLevels];
+#pragma unroll
+    for (int t = 0; t < KM; ++t) {
+        inv[t] = K > 1 ? T[(0 * (K - 1) + t) * 64 + lane] : 0.f;
+        ee[t] = K > 1 ? T[(1 * (K - 1) + t) * 64 + lane] : 0.f;
+        al[t] = K > 1 ? T[(2 * (K - 1) + t) * 64 + lane] : 0.f;
+        be[t] = K > 1 ? T[(3 * (K - 1) + t) * 64 + lane] : 0.f;
+    }
+#pragma unroll
+    for (int v = 0; v < kXLaneLevels; ++v) {
+        k1[v] = T[(4 * (K - 1) + 2 * v) * 64 + lane];
+        k2[v] = T[(4 * (K - 1) + 2 * v + 1) * 64 + lane];
+    }
+    const float binv = T[(4 * (K - 1) + 2 * kXLaneLevels) * 64 + lane];
+    const float cprev = T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + lane];
+    const float cnext = T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + lane];
+
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(field + S.base, S.vol);
+    const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw ? raw + S.base : field + S.base, S.vol);
+    const unsigned lane_b = (unsigned)(K * lane) * 4u;
+
+    float rn[K];
+    if (row0 < nrows && act) xl_load<K>(rn, rs, (unsigned)row0 * (unsigned)nx * 4u + lane_b);
+    for (int g = 0; g < kTileLines / 4; ++g) {
+        const int row = row0 + g;
+        if (row >= nrows) break;  // wave-uniform
+        float r[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) r[t] = act ? rn[t] : 0.f;
+        if (row + 1 < nrows && g + 1 < kTileLines / 4 && act)
+            xl_load<K>(rn, rs, (unsigned)(row + 1) * (unsigned)nx * 4u + lane_b);
+
+        // Dirichlet projection before the solve: the end voxels of the line
+        if (n == 1) {
+            const int f0 = max(lo_f, hi_f);
+            if (f0 >= 0 && lane == 0) r[0] = S.dval32[f0];
+        } else {
+            if (lo_f >= 0 && lane == 0) r[0] = S.dval32[lo_f];
+            if (hi_f >= 0 && lane == P - 1) {
+#pragma unroll
+                for (int t = 0; t < K; ++t)
+                    if (t == m) r[t] = S.dval32[hi_f];
+            }
+        }
+
+        // the lane's interval: u = T_int^-1 r_int
+        float u[KM];
+        {
+            float y[KM];
+            float prev = 0.f;
+#pragma unroll
+            for (int t = 0; t < K - 1; ++t) {
+                prev = fmaf(ee[t], prev, r[t] * inv[t]);
+                y[t] = t < m ? prev : 0.f;
+            }
+            float nxt = 0.f;
+#pragma unroll
+            for (int t = K - 2; t >= 0; --t) {
+                nxt = t < m ? fmaf(ee[t], nxt, y[t]) : 0.f;
+                u[t] = nxt;
+            }
+            if (K == 1) u[0] = 0.f;
+        }
+        // the separator's right-hand side
+        float rsep = r[0], ulast = 0.f;
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+            if (t == m) rsep = r[t];
+#pragma unroll
+        for (int t = 0; t < K - 1; ++t)
+            if (t == m - 1) ulast = u[t];
+        const float ufirst_next = __shfl_down(u[0], 1, 64);
+        float d = act ? fmaf(cnext, ufirst_next, fmaf(cprev, ulast, rsep)) : 0.f;
+        // parallel cyclic reduction over the lanes
+#pragma unroll
+        for (int v = 0; v < kXLaneLevels; ++v) {
+            const int s = 1 << v;
+            if (s < P) {  // uniform
+                const float dl = __shfl_up(d, s, 64);
+                const float dr = __shfl_down(d, s, 64);
+                d = fmaf(-k2[v], dr, fmaf(-k1[v], dl, d));
+            }
+        }
+        const float xs = d * binv;
+        const float xl = __shfl_up(xs, 1, 64);
+        // the lane's voxels; decay once per step after the x solve
+        float o[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const float xi = (t < K - 1 && t < m) ? fmaf(be[t < KM ? t : 0], xs, fmaf(al[t < KM ? t : 0], xl, u[t < KM ? t : 0]))
+                                                  : xs;
+            o[t] = xi * fdec;
+        }
+        const unsigned voff = (unsigned)row * (unsigned)nx * 4u + lane_b;
+        if (raw && act) xl_store<K>(o, rr, voff, cnt);
+        // Dirichlet projection after the solve: whole line on a y/z face, then
+        // the ends on the x faces (the last active face in x-, x+, y-, y+, z-,
+        // z+ order wins)
+        const int j = row % ny, k = row / ny;
+        const int on = (j == 0 ? 1 << 2 : 0) | (j == ny - 1 ? 1 << 3 : 0) | (k == 0 ? 1 << 4 : 0) |
+                       (k == nz - 1 ? 1 << 5 : 0);
+        const int wface = top_face(dmask & on);
+        if (wface >= 0) {
+            const float wv = face_value(S.dval32, wface);
+#pragma unroll
+            for (int t = 0; t < K; ++t) o[t] = wv;
+        }
+        const int f_first = max(wface, max(lo_f, n == 1 ? hi_f : -1));
+        const int f_last = max(wface, hi_f);
+        if (lane == 0 && f_first >= 0) o[0] = face_value(S.dval32, f_first);
+        if (n > 1 && lane == P - 1 && f_last >= 0) {
+            const float ev = face_value(S.dval32, f_last);
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (t == m) o[t] = ev;
+        }
+        if (act) xl_store<K>(o, rs, voff, cnt);
+    }
+}
+
+hipError_t launch_sweep_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
+                           float *raw, hipStream_t st)
+{
+    if (L.total_tiles <= 0) return hipSuccess;
+    const dim3 grid(L.total_tiles), block(256);
+    switch (K) {
+#define VL_XL_CASE(k)                                                                                  \
+    case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, subs, xl32, field, raw); break;
+        VL_XL_CASE(1)
+        VL_XL_CASE(2)
+        VL_XL_CASE(3)
+        VL_XL_CASE(4)
+        VL_XL_CASE(5)
+        VL_XL_CASE(6)
+        VL_XL_CASE(7)
+        VL_XL_CASE(8)
+        VL_XL_CASE(9)
+#undef VL_XL_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vl

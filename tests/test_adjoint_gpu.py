@@ -40,10 +40,11 @@ def _oracle_grads(spec, target, mode, n_steps):
     return sim.adjoint(n_steps, r), r
 
 
-def _gpu_grads(specs, finals, mode, n_steps, ckpt):
+def _gpu_grads(specs, finals, mode, n_steps, ckpt, x_lanes=0):
     decay = vb.VL_DECAY_ONCE if mode == O.DECAY_ONCE else vb.VL_DECAY_THIRDS
     ctx = vb.Context(specs, decay_split=decay, device="cuda:0")
     try:
+        ctx.set_option(vb.VL_OPT_X_LANES, x_lanes)
         before = [ctx.get_field(k).copy() for k in range(len(specs))]
         g = ctx.adjoint(n_steps, ckpt, [f.astype(np.float32) for f in finals])
         out = [{k: (v.double().cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)) for k, v in d.items()}
@@ -85,6 +86,15 @@ def test_adjoint_matches_oracle(mode, shape, bc):
     o, r = _oracle_grads(spec, target, mode, n_steps)
     g = _gpu_grads([spec], [r], mode, n_steps, ckpt=3)[0]
     _compare(g, o, f"{shape} {bc} mode {mode}")
+
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_adjoint_with_x_lanes_forward(mode):
+    # forward steps and replays use the lanes-along-the-line x solve
+    spec, target = _case(123, (130, 13, 9), bc="mixed", n_cells=30)
+    o, r = _oracle_grads(spec, target, mode, 6)
+    g = _gpu_grads([spec], [r], mode, 6, ckpt=4, x_lanes=1)[0]
+    _compare(g, o, f"x lanes mode {mode}")
 
 
 @pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])

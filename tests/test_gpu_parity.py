@@ -58,6 +58,9 @@ def test_fp64_tiny_grids(shape, bc, decay):
 # FP32 path: line lengths around every split and capacity boundary
 
 LINE_LENGTHS = [1, 2, 3, 4, 5, 63, 64, 65, 66, 127, 128, 129, 130, 131, 193, 257, 258, 321, 401, 513]
+# x solve with lanes along the line: around every voxels-per-lane boundary
+X_LANE_LENGTHS = [1, 2, 3, 31, 63, 64, 65, 66, 127, 128, 129, 191, 192, 193, 200, 255, 256, 257,
+                  319, 320, 321, 383, 384, 385, 400, 447, 448, 449, 511, 512, 513]
 
 
 @pytest.mark.parametrize("n", LINE_LENGTHS)
@@ -71,32 +74,52 @@ def test_fp32_line_lengths(n, axis):
     assert_close(got, want, 1e-5, f"fp32 n={n} axis={axis}")
 
 
+@pytest.mark.parametrize("n", X_LANE_LENGTHS)
+@pytest.mark.parametrize("bc", ["mixed", "dirichlet"])
+def test_fp32_x_lanes_line_lengths(n, bc):
+    spec = _spec((n, 5, 3), 2, bc, 12, "f32", n * 7 + len(bc))
+    (got,), _ = run_gpu([spec], 20, x_lanes=1)
+    want = run_oracle(spec, 20)
+    assert_close(got, want, 1e-5, f"x lanes n={n} {bc}")
+
+
+@pytest.mark.parametrize("x_lanes", [0, 1])
 @pytest.mark.parametrize("decay", DECAYS)
 @pytest.mark.parametrize("bc", ["neumann", "dirichlet", "mixed"])
-def test_fp32_boundary_mixes_and_decay(bc, decay):
+def test_fp32_boundary_mixes_and_decay(bc, decay, x_lanes):
     spec = _spec((33, 70, 19), 3, bc, 400, "f32", 11, layout="gaussian")
-    (got,), _ = run_gpu([spec], 30, decay=decay[0])
+    (got,), _ = run_gpu([spec], 30, decay=decay[0], x_lanes=x_lanes)
     want = run_oracle(spec, 30, decay[1])
     assert_close(got, want, 1e-5, f"fp32 {bc}")
 
 
-def test_fp32_single_large_scaled_100_steps():
+@pytest.mark.parametrize("x_lanes", [0, 1])
+def test_fp32_single_large_scaled_100_steps(x_lanes):
     """The single large simulation at a quarter of its edge (50^3 x 4, Gaussian
     ball of cells), 100 steps."""
     wl = W.single_large(scale=0.25)
     spec = wl.sims[0]
-    (got,), _ = run_gpu([spec], 100)
+    (got,), _ = run_gpu([spec], 100, x_lanes=x_lanes)
     want = run_oracle(spec, 100)
     errs = assert_close(got, want, 1e-5, "single-large/4")
     print("single-large/4 errors per substrate (max, L2):", errs)
 
 
-def test_fp32_batched_ragged():
+@pytest.mark.parametrize("x_lanes", [0, 1])
+def test_fp32_batched_ragged(x_lanes):
     wl = W.batched(n_sims=6, edge_range=(7, 70), cells_range=(50, 800))
-    fields, n_out = run_gpu(wl.sims, 40)
+    fields, n_out = run_gpu(wl.sims, 40, x_lanes=x_lanes)
     assert n_out == [0] * 6
     for k, spec in enumerate(wl.sims):
         assert_close(fields[k], run_oracle(spec, 40), 1e-5, f"batch sim {k} {spec.shape}")
+
+
+def test_fp32_x_lanes_long_lines_100_steps():
+    """Long x-lines (400 voxels: seven per lane), 100 steps, Dirichlet and
+    zero-flux faces mixed."""
+    spec = _spec((400, 9, 7), 2, "mixed", 300, "f32", 4242)
+    (got,), _ = run_gpu([spec], 100, x_lanes=1)
+    assert_close(got, run_oracle(spec, 100), 1e-5, "x lanes 400")
 
 
 def test_fp64_batched_ragged():
@@ -198,8 +221,10 @@ def test_tuner_picks_a_mode_and_caches(tmp_path):
         fuse = ctx.get_option(vb.VL_OPT_FUSE_SOURCES)
         assert ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_LAUNCHES
         fxy = ctx.get_option(vb.VL_OPT_FUSE_XY)
+        xl = ctx.get_option(vb.VL_OPT_X_LANES)
         words = open(cache).read().split()
-        assert len(words) == 6 and int(words[3]) == xcd and int(words[4]) == fuse and int(words[5]) == fxy
+        assert len(words) == 7 and int(words[3]) == xcd and int(words[4]) == fuse and int(words[5]) == fxy
+        assert int(words[6]) == xl
         # a second context with the same shapes reads the choice back
         ctx2 = vb.Context(wl.sims)
         ctx2.set_option(vb.VL_OPT_XCD_ORDER, 1 - xcd)
@@ -209,7 +234,8 @@ def test_tuner_picks_a_mode_and_caches(tmp_path):
         assert ctx2.get_option(vb.VL_OPT_XCD_ORDER) == xcd
         assert ctx2.get_option(vb.VL_OPT_FUSE_SOURCES) == fuse
         assert ctx2.get_option(vb.VL_OPT_FUSE_XY) == fxy
-        assert len(open(cache).read().split()) == 6
+        assert ctx2.get_option(vb.VL_OPT_X_LANES) == xl
+        assert len(open(cache).read().split()) == 7
         # the tuned context still computes the step correctly
         for k, s in enumerate(wl.sims):
             ctx2.set_field(k, s.rho0)
@@ -335,6 +361,7 @@ def _run_xy(specs, steps, fuse_xy, decay=vb.VL_DECAY_ONCE):
     ctx = vb.Context(specs, decay_split=decay, device="cuda:0")
     try:
         ctx.set_option(vb.VL_OPT_FUSE_XY, fuse_xy)
+        ctx.set_option(vb.VL_OPT_X_LANES, 0)  # the plane kernel's x solve is the split one
         ctx.set_profiling(True)
         ctx.step(steps)
         ctx.sync()
