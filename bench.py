@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--no-copy-reference", action="store_true")
     ap.add_argument("--mode", default="tuned", choices=["tuned", "launches", "persistent"])
     ap.add_argument("--ckpt-every", type=int, default=20)
+    ap.add_argument("--x-lanes", default="auto", choices=["auto", "0", "1"],
+                    help="force the x solve (after tuning): 1 lanes along the line, 0 split solve")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
@@ -291,6 +293,8 @@ def main():
     else:
         ctx.set_option(vb.VL_OPT_STEP_MODE,
                        vb.VL_MODE_PERSISTENT if args.mode == "persistent" else vb.VL_MODE_LAUNCHES)
+    if args.x_lanes != "auto" and precision == vb.VL_F32:
+        ctx.set_option(vb.VL_OPT_X_LANES, int(args.x_lanes))
     mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
     fuse_src = bool(ctx.get_option(vb.VL_OPT_FUSE_SOURCES))
     xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))

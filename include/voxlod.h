@@ -215,15 +215,16 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * are as fast or faster; vl_tune times both.  Without the device's support
  * for that much LDS per workgroup the option has no effect. */
 #define VL_OPT_FUSE_XY 6
-/* VL_OPT_X_LANES (FP32 path, default 0): 1 solves the x-lines with the lanes
- * of a wave along one line (each lane K = ceil(nx/64) consecutive voxels,
- * wide coalesced loads and stores, no LDS transpose): each lane eliminates
- * its run locally and the runs' last voxels form a tridiagonal system over
- * the lanes, solved by parallel cyclic reduction with multipliers computed
- * in FP64 when the coefficients are (vl_bind, vl_update_substrates).  The
- * same linear system as the split solve, to rounding.  Used when x and y are
- * not solved per plane; the adjoint's replay follows it.  vl_tune times
- * both. */
+/* VL_OPT_X_LANES (FP32 path, default 1): 1 solves x-lines of 129 or more
+ * voxels with the lanes of a wave along one line (each lane 4 consecutive
+ * voxels for lines up to 256, 8 up to 512, 9 beyond; wide coalesced loads and
+ * stores, no LDS transpose): each lane eliminates its run locally and the
+ * runs' last voxels form a tridiagonal system over the lanes, solved by
+ * parallel cyclic reduction with multipliers computed in FP64 when the
+ * coefficients are (vl_bind, vl_update_substrates).  The same linear system
+ * as the split solve, to rounding.  Shorter lines keep the split solve.
+ * Used when x and y are not solved per plane; the adjoint's replay follows
+ * it.  0 uses the split solve for every line; vl_tune times both. */
 #define VL_OPT_X_LANES 7
 /* Selecting VL_MODE_PERSISTENT currently fails with VL_E_STATE: the one-launch
  * step is switched off until a hang seen in its first GPU runs is explained. */

@@ -68,8 +68,10 @@ struct SubDev {
 //                              is not empty, else 0
 constexpr int kXLaneMaxK = 9;  // lines of up to 576 voxels
 constexpr int kXLaneLevels = 6;
+constexpr int kXLaneMinN = 129;  // shorter lines keep the split solve (few voxels per lane)
 __host__ __device__ constexpr int xl_fields(int K) { return 4 * (K - 1) + 2 * kXLaneLevels + 3; }
-__host__ __device__ constexpr int xl_k(int n) { return n <= 64 ? 1 : (n + 63) / 64; }
+// voxels per lane: whole 16-byte pieces where the line allows
+__host__ __device__ constexpr int xl_k(int n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 9; }
 
 // One launch of an FP32 sweep over a group of volumes sharing a capacity
 // class: tiles of the listed volumes are numbered consecutively.

@@ -109,8 +109,9 @@ struct vl_ctx {
     std::vector<Launch> xy_launches;
     // x solve with lanes along the line: launches grouped by voxels per lane
     // (cap_idx holds K) and the per-volume tables
-    bool x_lanes = false;
-    std::vector<Launch> xl_launches;
+    bool x_lanes = true;
+    std::vector<Launch> xl_launches;       // long lines: lanes along the line
+    std::vector<Launch> xl_rest_launches;  // the other volumes' split x sweeps
     size_t n_xl32 = 0;
     size_t xy_lds_max = 0;
     bool xcd_order = true;
@@ -291,6 +292,8 @@ int enqueue_step(vl_ctx *ctx)
         };
         for (int axis = 0; axis < 3; ++axis) {
             if (!xy && axis == 0 && ctx->x_lanes) {
+                for (const Launch &L : ctx->xl_rest_launches)
+                    if ((rc = sweep(L))) return rc;
                 for (const Launch &L : ctx->xl_launches) {
                     vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
                                       ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
@@ -674,13 +677,39 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             ctx->xy_lds_max = std::max(ctx->xy_lds_max, lds);
         }
     }
-    // x with lanes along the line: volumes grouped by voxels per lane
+    // x with lanes along the line: volumes with lines of at least
+    // kXLaneMinN voxels grouped by voxels per lane; the split x sweeps of the
+    // others
     ctx->xl_launches.clear();
+    ctx->xl_rest_launches.clear();
     if (ctx->precision == VL_F32) {
+        auto long_x = [&](int q) { return ctx->subs[q].xlane >= 0 && ctx->subs[q].n[0] >= vl::kXLaneMinN; };
+        std::vector<std::vector<int>> groups(vl::kNumCaps);
+        for (int q = 0; q < nsubs; ++q)
+            if (!long_x(q)) groups[cap_index(ctx->subs[q].n[0] - 1 - (ctx->subs[q].n[0] - 1) / 2)].push_back(q);
+        for (int ci = 0; ci < vl::kNumCaps; ++ci) {
+            if (groups[ci].empty()) continue;
+            Launch L;
+            L.axis = 0;
+            L.cap_idx = ci;
+            L.count = (int)groups[ci].size();
+            L.ids_off = ctx->itable.size();
+            for (int q : groups[ci]) ctx->itable.push_back(q);
+            L.prefix_off = ctx->itable.size();
+            long long acc = 0;
+            for (int q : groups[ci]) {
+                ctx->itable.push_back((int)acc);
+                const SubDev &d = ctx->subs[q];
+                acc += (d.vol / d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
+            }
+            ctx->itable.push_back((int)acc);
+            L.total_tiles = (int)acc;
+            ctx->xl_rest_launches.push_back(L);
+        }
         for (int K = 1; K <= vl::kXLaneMaxK; ++K) {
             std::vector<int> ids;
             for (int q = 0; q < nsubs; ++q)
-                if (ctx->subs[q].xlane >= 0 && vl::xl_k(ctx->subs[q].n[0]) == K) ids.push_back(q);
+                if (long_x(q) && vl::xl_k(ctx->subs[q].n[0]) == K) ids.push_back(q);
             if (ids.empty()) continue;
             Launch L;
             L.axis = 0;
@@ -1437,25 +1466,38 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
     float *field = (float *)ctx->field;
     const vl::FusedSources nosrc{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
                                  ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0};
-    for (int axis = 0; axis < 3; ++axis)
-        for (const Launch &L : (axis == 0 && ctx->x_lanes) ? ctx->xl_launches : ctx->launches) {
-            if (L.axis != axis) continue;
-            vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
-                              L.count, L.total_tiles, 1};
-            if (axis == 0 && ctx->x_lanes) {
-                if (int rc = timed(ctx, VL_K_REPLAY_X, [&] {
-                        return vl::launch_sweep_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), field,
-                                                   (float *)(aws + A.raw[0]), st);
-                    }))
-                    return rc;
-                continue;
-            }
-            if (int rc = timed(ctx, VL_K_REPLAY_X + axis, [&] {
-                    return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
-                                                nosrc, st);
+    // x: the lanes-along-the-line solve for long lines when selected, the
+    // split sweeps otherwise; then y and z
+    std::vector<std::pair<const Launch *, bool>> order;  // (launch, lanes along the line)
+    if (ctx->x_lanes) {
+        for (const Launch &L : ctx->xl_rest_launches) order.push_back({&L, false});
+        for (const Launch &L : ctx->xl_launches) order.push_back({&L, true});
+    } else {
+        for (const Launch &L : ctx->launches)
+            if (L.axis == 0) order.push_back({&L, false});
+    }
+    for (int axis = 1; axis < 3; ++axis)
+        for (const Launch &L : ctx->launches)
+            if (L.axis == axis) order.push_back({&L, false});
+    for (const auto &o : order) {
+        const Launch &L = *o.first;
+        const int axis = L.axis;
+        vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
+                          L.count, L.total_tiles, 1};
+        if (o.second) {
+            if (int rc = timed(ctx, VL_K_REPLAY_X, [&] {
+                    return vl::launch_sweep_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), field,
+                                               (float *)(aws + A.raw[0]), st);
                 }))
                 return rc;
+            continue;
         }
+        if (int rc = timed(ctx, VL_K_REPLAY_X + axis, [&] {
+                return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
+                                            nosrc, st);
+            }))
+            return rc;
+    }
     return VL_OK;
 }
 

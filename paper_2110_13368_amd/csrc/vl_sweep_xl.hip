@@ -1,9 +1,9 @@
 // vl_sweep_xl.hip -- the x solve with lanes along the line.
 //
 // x-lines are contiguous, so instead of transposing 64 lines through LDS (one
-// line per lane, as the split sweep does), lane l of a wave holds K =
-// ceil(nx/64) consecutive voxels of ONE line, loaded and stored with wide,
-// fully coalesced buffer instructions.  The line matrix T = tridiag(-c, b, -c)
+// line per lane, as the split sweep does), lane l of a wave holds K
+// consecutive voxels of ONE line (K = 4 for lines of 129-256 voxels, 8 up to
+// 512), loaded and stored with wide, fully coalesced buffer instructions.  The line matrix T = tridiag(-c, b, -c)
 // is solved by substructuring:
 //   * the last voxel of each lane's run is a separator; the voxels before it
 //     form the lane's interval, eliminated locally (x_int = u + al*x_left +
@@ -249,16 +249,22 @@ sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict
     const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw ? raw + S.base : field + S.base, S.vol);
     const unsigned lane_b = (unsigned)(K * lane) * 4u;
 
-    float rn[K];
-    if (row0 < nrows && act) xl_load<K>(rn, rs, (unsigned)row0 * (unsigned)nx * 4u + lane_b);
-    for (int g = 0; g < kTileLines / 4; ++g) {
+    // two lines in flight ahead of the one being solved
+    constexpr int kLines = kTileLines / 4;
+    float rn1[K], rn2[K];
+    if (row0 < nrows && act) xl_load<K>(rn1, rs, (unsigned)row0 * (unsigned)nx * 4u + lane_b);
+    if (row0 + 1 < nrows && act) xl_load<K>(rn2, rs, (unsigned)(row0 + 1) * (unsigned)nx * 4u + lane_b);
+    for (int g = 0; g < kLines; ++g) {
         const int row = row0 + g;
         if (row >= nrows) break;  // wave-uniform
         float r[K];
 #pragma unroll
-        for (int t = 0; t < K; ++t) r[t] = act ? rn[t] : 0.f;
-        if (row + 1 < nrows && g + 1 < kTileLines / 4 && act)
-            xl_load<K>(rn, rs, (unsigned)(row + 1) * (unsigned)nx * 4u + lane_b);
+        for (int t = 0; t < K; ++t) {
+            r[t] = act ? rn1[t] : 0.f;
+            rn1[t] = rn2[t];
+        }
+        if (row + 2 < nrows && g + 2 < kLines && act)
+            xl_load<K>(rn2, rs, (unsigned)(row + 2) * (unsigned)nx * 4u + lane_b);
 
         // Dirichlet projection before the solve: the end voxels of the line
         if (n == 1) {
@@ -358,11 +364,7 @@ hipError_t launch_sweep_xl(int K, const SweepLaunch &L, const SubDev *subs, cons
     case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, subs, xl32, field, raw); break;
         VL_XL_CASE(1)
         VL_XL_CASE(2)
-        VL_XL_CASE(3)
         VL_XL_CASE(4)
-        VL_XL_CASE(5)
-        VL_XL_CASE(6)
-        VL_XL_CASE(7)
         VL_XL_CASE(8)
         VL_XL_CASE(9)
 #undef VL_XL_CASE

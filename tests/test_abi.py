@@ -111,9 +111,9 @@ def test_options_on_the_host():
         vb.vl_set_option(h, vb.VL_OPT_FUSE_XY, 1)
         assert vb.vl_get_option(h, vb.VL_OPT_FUSE_XY) == 1
         assert _code(vb.vl_set_option, h, vb.VL_OPT_FUSE_XY, 3) == vb.VL_E_ARG
-        assert vb.vl_get_option(h, vb.VL_OPT_X_LANES) == 0
-        vb.vl_set_option(h, vb.VL_OPT_X_LANES, 1)
         assert vb.vl_get_option(h, vb.VL_OPT_X_LANES) == 1
+        vb.vl_set_option(h, vb.VL_OPT_X_LANES, 0)
+        assert vb.vl_get_option(h, vb.VL_OPT_X_LANES) == 0
         assert _code(vb.vl_set_option, h, vb.VL_OPT_X_LANES, -1) == vb.VL_E_ARG
         vb.vl_set_option(h, vb.VL_OPT_XCD_ORDER, 0)
         assert vb.vl_get_option(h, vb.VL_OPT_XCD_ORDER) == 0
