@@ -3,7 +3,8 @@
 // x-lines are contiguous, so instead of transposing 64 lines through LDS (one
 // line per lane, as the split sweep does), lane l of a wave holds K
 // consecutive voxels of ONE line (K = 4 for lines of 129-256 voxels, 8 up to
-// 512), loaded and stored with wide, fully coalesced buffer instructions.  The line matrix T = tridiag(-c, b, -c)
+// 512, 9 for 513), loaded and stored with wide, fully coalesced buffer
+// instructions.  The line matrix T = tridiag(-c, b, -c)
 // is solved by substructuring:
 //   * the last voxel of each lane's run is a separator; the voxels before it
 //     form the lane's interval, eliminated locally (x_int = u + al*x_left +

@@ -115,7 +115,7 @@ def test_fp32_batched_ragged(x_lanes):
 
 
 def test_fp32_x_lanes_long_lines_100_steps():
-    """Long x-lines (400 voxels: seven per lane), 100 steps, Dirichlet and
+    """Long x-lines (400 voxels: eight per lane), 100 steps, Dirichlet and
     zero-flux faces mixed."""
     spec = _spec((400, 9, 7), 2, "mixed", 300, "f32", 4242)
     (got,), _ = run_gpu([spec], 100, x_lanes=1)
