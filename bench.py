@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=20)
     ap.add_argument("--x-lanes", default="auto", choices=["auto", "0", "1"],
                     help="force the x solve (after tuning): 1 lanes along the line, 0 split solve")
+    ap.add_argument("--x-lane-lines", default="auto", choices=["auto", "1", "2", "4", "8", "16"],
+                    help="force the x-lines per wave of the lanes-along-the-line solve (after tuning)")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
@@ -295,10 +297,13 @@ def main():
                        vb.VL_MODE_PERSISTENT if args.mode == "persistent" else vb.VL_MODE_LAUNCHES)
     if args.x_lanes != "auto" and precision == vb.VL_F32:
         ctx.set_option(vb.VL_OPT_X_LANES, int(args.x_lanes))
+    if args.x_lane_lines != "auto" and precision == vb.VL_F32:
+        ctx.set_option(vb.VL_OPT_X_LANE_LINES, int(args.x_lane_lines))
     mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
     fuse_src = bool(ctx.get_option(vb.VL_OPT_FUSE_SOURCES))
     xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))
     x_lanes = bool(ctx.get_option(vb.VL_OPT_X_LANES)) if precision == vb.VL_F32 else False
+    x_lane_lines = ctx.get_option(vb.VL_OPT_X_LANE_LINES) if x_lanes else None
     for k, s in enumerate(wl.sims):
         ctx.set_field(k, s.rho0)
     elapsed = time_steps(ctx, args.steps, args.warmup)
@@ -374,7 +379,7 @@ def main():
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
                    "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode,
                    "xy_per_plane": fused_xy, "fuse_sources": fuse_src, "xcd_order": xcd_ord,
-                   "x_lanes_along_line": x_lanes},
+                   "x_lanes_along_line": x_lanes, "x_lines_per_wave": x_lane_lines},
         "hbm_effective": {"basis": "B_alg: three sweeps x (read + write) per voxel-substrate-step; with x and y "
                                    "solved per z-plane the step moves less than B_alg",
                           "bytes_per_update": b_alg,

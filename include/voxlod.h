@@ -226,14 +226,22 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * Used when x and y are not solved per plane; the adjoint's replay follows
  * it.  0 uses the split solve for every line; vl_tune times both. */
 #define VL_OPT_X_LANES 7
+/* VL_OPT_X_LANE_LINES (FP32 path, default 8): x-lines each wave of that
+ * solve takes one after another: 1, 2, 4, 8 or 16.  A workgroup is four
+ * waves, so a launch has (lines / (4 * value)) workgroups: small values give
+ * many short workgroups (a short tail when the grid is only a few rounds of
+ * the device), large ones keep more loads in flight per wave.  Fields do not
+ * depend on it; vl_tune times the candidates. */
+#define VL_OPT_X_LANE_LINES 8
 /* Selecting VL_MODE_PERSISTENT currently fails with VL_E_STATE: the one-launch
  * step is switched off until a hang seen in its first GPU runs is explained. */
 int vl_set_option(vl_ctx *ctx, int option, int value);
 int vl_get_option(vl_ctx *ctx, int option, int *value);
 
 /* Autotuner: times the candidate launch configurations (x+y per z-plane or
- * separate sweeps, XCD tile order on or off, sources fused into the z sweep
- * or separate) on the bound buffers, a
+ * separate sweeps, x lanes along the line or the split x solve and its lines
+ * per wave, XCD tile order on or off, sources fused into the z sweep or
+ * separate) on the bound buffers, a
  * few steps each (which overwrite the field), and keeps the fastest.  With a
  * non-NULL cache_path the choice is read from / appended to that text file,
  * keyed by precision, decay split and every volume's shape, so a second call

@@ -137,7 +137,7 @@ hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev 
 // x-lines as for the split sweep).  raw as for launch_sweep_f32.
 hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *coef_unused, float *xl32,
                             hipStream_t st);
-hipError_t launch_sweep_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
+hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
                            float *raw, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.

@@ -14,6 +14,9 @@
 
 using vl::SubDev;
 
+// x-lines per wave of the lanes-along-the-line solve when not tuned
+constexpr int kDefaultXLaneLines = 8;
+
 namespace {
 
 thread_local std::string g_err;
@@ -110,6 +113,7 @@ struct vl_ctx {
     // x solve with lanes along the line: launches grouped by voxels per lane
     // (cap_idx holds K) and the per-volume tables
     bool x_lanes = true;
+    int xl_lpw = kDefaultXLaneLines;  // x-lines per wave of the lanes-along-the-line solve
     std::vector<Launch> xl_launches;       // long lines: lanes along the line
     std::vector<Launch> xl_rest_launches;  // the other volumes' split x sweeps
     size_t n_xl32 = 0;
@@ -299,7 +303,8 @@ int enqueue_step(vl_ctx *ctx)
                                       ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
                                       ctx->xcd_order ? 1 : 0};
                     rc = timed(ctx, VL_K_SWEEP_X, [&] {
-                        return vl::launch_sweep_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), field, nullptr, st);
+                        return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<float>(ctx->o_xl32),
+                                                   field, nullptr, st);
                     });
                     if (rc) return rc;
                 }
@@ -1221,6 +1226,13 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         ctx->x_lanes = value == 1;
         return VL_OK;
     }
+    if (option == VL_OPT_X_LANE_LINES) {
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+            return fail(VL_E_ARG, "VL_OPT_X_LANE_LINES takes 1, 2, 4, 8 or 16");
+        if (ctx->xl_lpw != value) drop_graph(ctx);
+        ctx->xl_lpw = value;
+        return VL_OK;
+    }
     if (option == VL_OPT_FUSE_XY) {
         if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_FUSE_XY takes 0 or 1");
         if (ctx->fuse_xy != (value == 1)) drop_graph(ctx);
@@ -1254,6 +1266,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     case VL_OPT_XCD_ORDER: *value = ctx->xcd_order ? 1 : 0; return VL_OK;
     case VL_OPT_FUSE_XY: *value = ctx->fuse_xy ? 1 : 0; return VL_OK;
     case VL_OPT_X_LANES: *value = ctx->x_lanes ? 1 : 0; return VL_OK;
+    case VL_OPT_X_LANE_LINES: *value = ctx->xl_lpw; return VL_OK;
     default: return fail(VL_E_ARG, "unknown option");
     }
 }
@@ -1288,9 +1301,9 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     if (ctx->precision != VL_F32) return VL_OK;  // the plain path has one shape
     const std::string key = tune_key(ctx);
     // a candidate: step mode, its grid, XCD-ordered tiles, fused sources,
-    // x+y per z-plane
+    // x+y per z-plane, x lanes along the line and their lines per wave
     struct Cand {
-        int mode, grid, xcd, fuse, xy, xl;
+        int mode, grid, xcd, fuse, xy, xl, lpw;
     };
     auto apply = [&](const Cand &c) -> int {
         if (int rc = vl_set_option(ctx, VL_OPT_STEP_MODE, c.mode)) return rc;
@@ -1298,14 +1311,16 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
         if (int rc = vl_set_option(ctx, VL_OPT_XCD_ORDER, c.xcd)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_FUSE_XY, c.xy)) return rc;
         if (int rc = vl_set_option(ctx, VL_OPT_X_LANES, c.xl)) return rc;
+        if (int rc = vl_set_option(ctx, VL_OPT_X_LANE_LINES, c.lpw)) return rc;
         return vl_set_option(ctx, VL_OPT_FUSE_SOURCES, c.fuse);
     };
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "r")) {
             char k[128];
-            Cand c{0, 0, 1, 1, 0, 0};
+            Cand c{0, 0, 1, 1, 0, 0, kDefaultXLaneLines};
             bool hit = false;
-            while (std::fscanf(f, "%127s %d %d %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse, &c.xy, &c.xl) == 7)
+            while (std::fscanf(f, "%127s %d %d %d %d %d %d %d", k, &c.mode, &c.grid, &c.xcd, &c.fuse, &c.xy, &c.xl,
+                               &c.lpw) == 8)
                 if (key == k) {
                     hit = true;
                     break;
@@ -1319,14 +1334,17 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     for (int xy = any_plane ? 1 : 0; xy >= 0; --xy)
         for (int xl = xy ? 0 : 1; xl >= 0; --xl)
             for (int xcd = 1; xcd >= 0; --xcd)
-                for (int fuse = 1; fuse >= 0; --fuse) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl});
+                for (int fuse = 1; fuse >= 0; --fuse) {
+                    cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, kDefaultXLaneLines});
+                    if (xl && xcd) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, 16});
+                }
     if (one_launch_enabled()) {
         int per_cu = 1, cus = 1, dev = 0;
         VL_HIP(hipGetDevice(&dev));
         VL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         VL_HIP(vl::persistent_blocks_per_cu(ctx->queue_cap_idx, &per_cu));
         per_cu = std::max(per_cu, 1);
-        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1, 0, 0});
+        cands.push_back({VL_MODE_PERSISTENT, per_cu * cus, 1, 1, 0, 0, kDefaultXLaneLines});
     }
     const bool was_profiling = ctx->profiling;
     ctx->profiling = false;
@@ -1367,8 +1385,8 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     if ((rc = apply(pick))) return rc;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse, pick.xy,
-                         pick.xl);
+            std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), pick.mode, pick.grid, pick.xcd, pick.fuse,
+                         pick.xy, pick.xl, pick.lpw);
             std::fclose(f);
         }
     }
@@ -1486,7 +1504,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
                           L.count, L.total_tiles, 1};
         if (o.second) {
             if (int rc = timed(ctx, VL_K_REPLAY_X, [&] {
-                    return vl::launch_sweep_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), field,
+                    return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<float>(ctx->o_xl32), field,
                                                (float *)(aws + A.raw[0]), st);
                 }))
                 return rc;

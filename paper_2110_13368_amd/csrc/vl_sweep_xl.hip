@@ -18,6 +18,8 @@
 // system; the order of operations differs from the split Thomas sweep).
 // Decay (once per step) multiplies the solution by f; the Dirichlet projection
 // before and after is applied as in the other sweeps.
+#include <type_traits>
+
 #include "vl_device.h"
 
 namespace vl {
@@ -153,9 +155,12 @@ hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *, float
 }
 
 // ---------------------------------------------------------------------------
-// The sweep.  A workgroup of four waves takes one tile of 64 x-lines (the
-// split sweep's tiling); each wave solves 16 of them one after another, with
-// the next line's load issued before the current line is solved.
+// The sweep.  The launch covers tiles of 64 x-lines (the split sweep's
+// tiling); 16 / lpw workgroups of four waves share a tile, and each wave
+// solves lpw consecutive lines one after another, with the loads of the next
+// two lines issued before the current line is solved.  Fewer lines per wave
+// make more, shorter-lived workgroups (a shorter tail at the end of the
+// launch); more lines per wave hide more load latency within a wave.
 
 template <int K>
 __device__ __forceinline__ void xl_load(float (&r)[K], __amdgpu_buffer_rsrc_t rs, unsigned voff)
@@ -202,13 +207,17 @@ __device__ __forceinline__ void xl_store(const float (&o)[K], __amdgpu_buffer_rs
     }
 }
 
+constexpr int kXlAhead = 2;
+
 template <int K>
 __global__ void __launch_bounds__(256)
-sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict__ xl32,
+sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *__restrict__ xl32,
          float *__restrict__ field, float *__restrict__ raw)
 {
     constexpr int KM = K > 1 ? K - 1 : 1;
-    const int tile = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int parts = (kTileLines / 4) / lpw;  // workgroups per tile
+    const int blk = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = blk / parts, part = blk - tile * parts;
     const int slot = find_slot(L.tile_prefix, L.count, tile);
     const int local = tile - L.tile_prefix[slot];
     const SubDev &S = subs[L.sub_ids[slot]];
@@ -221,7 +230,7 @@ sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict
     const int m = act ? min(K * lane + K - 1, n - 1) - K * lane : 0;  // interval length
     const int cnt = act ? m + 1 : 0;                                   // voxels of this lane
     const int nrows = ny * nz;
-    const int row0 = local * kTileLines + wave * (kTileLines / 4);
+    const int row0 = local * kTileLines + (part * 4 + wave) * lpw;
     const int dmask = S.dir_mask;
     const int lo_f = (dmask & 1) ? 0 : -1;
     const int hi_f = (dmask & 2) ? 1 : -1;
@@ -250,35 +259,53 @@ sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict
     const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw ? raw + S.base : field + S.base, S.vol);
     const unsigned lane_b = (unsigned)(K * lane) * 4u;
 
-    // two lines in flight ahead of the one being solved
-    constexpr int kLines = kTileLines / 4;
-    float rn1[K], rn2[K];
-    if (row0 < nrows && act) xl_load<K>(rn1, rs, (unsigned)row0 * (unsigned)nx * 4u + lane_b);
-    if (row0 + 1 < nrows && act) xl_load<K>(rn2, rs, (unsigned)(row0 + 1) * (unsigned)nx * 4u + lane_b);
-    for (int g = 0; g < kLines; ++g) {
-        const int row = row0 + g;
-        if (row >= nrows) break;  // wave-uniform
-        float r[K];
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-            r[t] = act ? rn1[t] : 0.f;
-            rn1[t] = rn2[t];
-        }
-        if (row + 2 < nrows && g + 2 < kLines && act)
-            xl_load<K>(rn2, rs, (unsigned)(row + 2) * (unsigned)nx * 4u + lane_b);
+    // Dirichlet values and which lanes they go to, fixed for the launch, so
+    // that the per-line code below has no divergent branches
+    const float fv0 = S.dval32[0], fv1 = S.dval32[1], fv2 = S.dval32[2], fv3 = S.dval32[3], fv4 = S.dval32[4],
+                fv5 = S.dval32[5];
+    auto fval = [&](int f) {  // value of face f (uniform), 0 <= f < 6
+        return f == 5 ? fv5 : f == 4 ? fv4 : f == 3 ? fv3 : f == 2 ? fv2 : f == 1 ? fv1 : fv0;
+    };
+    const int f_in_lo = n == 1 ? max(lo_f, hi_f) : lo_f;  // before the solve, first voxel
+    const float v_in_lo = fval(f_in_lo);
+    const bool set_in_lo = lane == 0 && f_in_lo >= 0;
+    const bool set_in_hi = n > 1 && hi_f >= 0 && lane == P - 1;  // before the solve, last voxel
+    const float v_in_hi = fv1;
+    const bool last_lane = n > 1 && lane == P - 1;
 
-        // Dirichlet projection before the solve: the end voxels of the line
-        if (n == 1) {
-            const int f0 = max(lo_f, hi_f);
-            if (f0 >= 0 && lane == 0) r[0] = S.dval32[f0];
-        } else {
-            if (lo_f >= 0 && lane == 0) r[0] = S.dval32[lo_f];
-            if (hi_f >= 0 && lane == P - 1) {
+    // A lane's byte offset of a line, or one past any buffer when the line is
+    // not to be touched: buffer loads there return 0 and stores are dropped
+    // by the hardware's range check, so no lane needs a branch around them.
+    constexpr unsigned kOff = 0x80000000u;
+    auto line_off = [&](int row, bool want) -> unsigned {
+        return (want && act) ? (unsigned)row * (unsigned)nx * 4u + lane_b : kOff;
+    };
+
+    // Lane addresses of the shuffles, fixed for the launch; as with
+    // __shfl_up / __shfl_down, a lane with no source lane reads its own value.
+    int a_up[kXLaneLevels], a_dn[kXLaneLevels];
 #pragma unroll
-                for (int t = 0; t < K; ++t)
-                    if (t == m) r[t] = S.dval32[hi_f];
-            }
-        }
+    for (int v = 0; v < kXLaneLevels; ++v) {
+        const int s = 1 << v;
+        a_up[v] = (lane >= s ? lane - s : lane) << 2;
+        a_dn[v] = (lane + s < 64 ? lane + s : lane) << 2;
+    }
+    auto from_lane = [](int addr, float x) {
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+    };
+    // faces of the first and last voxel of a line on no y/z Dirichlet face
+    const int f_first0 = max(lo_f, n == 1 ? hi_f : -1), f_last0 = hi_f;
+    const float v_first0 = fval(f_first0), v_last0 = fval(f_last0);
+
+    // One line.  With FULL (n a multiple of K) every active lane holds K
+    // voxels, so the per-lane interval length is the constant K - 1.
+    auto solve_line = [&](auto full_c, const int row, const int j, const int k, float (&r)[K]) {
+        constexpr bool FULL = decltype(full_c)::value;
+        const int mm = FULL ? K - 1 : m;
+        // Dirichlet projection before the solve: the end voxels of the line
+        r[0] = set_in_lo ? v_in_lo : r[0];
+#pragma unroll
+        for (int t = 0; t < K; ++t) r[t] = (set_in_hi && t == mm) ? v_in_hi : r[t];
 
         // the lane's interval: u = T_int^-1 r_int
         float u[KM];
@@ -288,12 +315,12 @@ sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict
 #pragma unroll
             for (int t = 0; t < K - 1; ++t) {
                 prev = fmaf(ee[t], prev, r[t] * inv[t]);
-                y[t] = t < m ? prev : 0.f;
+                y[t] = t < mm ? prev : 0.f;
             }
             float nxt = 0.f;
 #pragma unroll
             for (int t = K - 2; t >= 0; --t) {
-                nxt = t < m ? fmaf(ee[t], nxt, y[t]) : 0.f;
+                nxt = t < mm ? fmaf(ee[t], nxt, y[t]) : 0.f;
                 u[t] = nxt;
             }
             if (K == 1) u[0] = 0.f;
@@ -302,67 +329,102 @@ sweep_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restrict
         float rsep = r[0], ulast = 0.f;
 #pragma unroll
         for (int t = 0; t < K; ++t)
-            if (t == m) rsep = r[t];
+            if (t == mm) rsep = r[t];
 #pragma unroll
         for (int t = 0; t < K - 1; ++t)
-            if (t == m - 1) ulast = u[t];
-        const float ufirst_next = __shfl_down(u[0], 1, 64);
+            if (t == mm - 1) ulast = u[t];
+        const float ufirst_next = from_lane(a_dn[0], u[0]);
         float d = act ? fmaf(cnext, ufirst_next, fmaf(cprev, ulast, rsep)) : 0.f;
-        // parallel cyclic reduction over the lanes
+        // parallel cyclic reduction over the lanes (a level whose distance
+        // reaches past the last lane has zero multipliers)
 #pragma unroll
         for (int v = 0; v < kXLaneLevels; ++v) {
-            const int s = 1 << v;
-            if (s < P) {  // uniform
-                const float dl = __shfl_up(d, s, 64);
-                const float dr = __shfl_down(d, s, 64);
-                d = fmaf(-k2[v], dr, fmaf(-k1[v], dl, d));
-            }
+            const float dl = from_lane(a_up[v], d);
+            const float dr = from_lane(a_dn[v], d);
+            d = fmaf(-k2[v], dr, fmaf(-k1[v], dl, d));
         }
         const float xs = d * binv;
-        const float xl = __shfl_up(xs, 1, 64);
+        const float xl = from_lane(a_up[0], xs);
         // the lane's voxels; decay once per step after the x solve
         float o[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-            const float xi = (t < K - 1 && t < m) ? fmaf(be[t < KM ? t : 0], xs, fmaf(al[t < KM ? t : 0], xl, u[t < KM ? t : 0]))
-                                                  : xs;
+            const float xi = (t < K - 1 && t < mm) ? fmaf(be[t < KM ? t : 0], xs, fmaf(al[t < KM ? t : 0], xl, u[t < KM ? t : 0]))
+                                                   : xs;
             o[t] = xi * fdec;
         }
-        const unsigned voff = (unsigned)row * (unsigned)nx * 4u + lane_b;
-        if (raw && act) xl_store<K>(o, rr, voff, cnt);
+        const unsigned voff = line_off(row, true);
+        if (raw) {  // uniform
+            if (FULL) xl_store<K>(o, rr, voff, K);
+            else if (act) xl_store<K>(o, rr, voff, cnt);
+        }
         // Dirichlet projection after the solve: whole line on a y/z face, then
         // the ends on the x faces (the last active face in x-, x+, y-, y+, z-,
-        // z+ order wins)
-        const int j = row % ny, k = row / ny;
+        // z+ order wins); the faces are uniform across the wave
         const int on = (j == 0 ? 1 << 2 : 0) | (j == ny - 1 ? 1 << 3 : 0) | (k == 0 ? 1 << 4 : 0) |
                        (k == nz - 1 ? 1 << 5 : 0);
         const int wface = top_face(dmask & on);
-        if (wface >= 0) {
-            const float wv = face_value(S.dval32, wface);
+        int f_first = f_first0, f_last = f_last0;
+        float v_first = v_first0, v_last = v_last0;
+        if (wface >= 0) {  // uniform
+            const float wv = fval(wface);
 #pragma unroll
             for (int t = 0; t < K; ++t) o[t] = wv;
+            f_first = max(wface, f_first0);
+            f_last = max(wface, f_last0);
+            v_first = fval(f_first);
+            v_last = fval(f_last);
         }
-        const int f_first = max(wface, max(lo_f, n == 1 ? hi_f : -1));
-        const int f_last = max(wface, hi_f);
-        if (lane == 0 && f_first >= 0) o[0] = face_value(S.dval32, f_first);
-        if (n > 1 && lane == P - 1 && f_last >= 0) {
-            const float ev = face_value(S.dval32, f_last);
+        o[0] = (lane == 0 && f_first >= 0) ? v_first : o[0];
 #pragma unroll
-            for (int t = 0; t < K; ++t)
-                if (t == m) o[t] = ev;
+        for (int t = 0; t < K; ++t) o[t] = (last_lane && f_last >= 0 && t == mm) ? v_last : o[t];
+        if (FULL) xl_store<K>(o, rs, voff, K);
+        else if (act) xl_store<K>(o, rs, voff, cnt);
+    };
+
+    // A ring of kXlAhead + 1 line slots, unrolled so that every slot has
+    // fixed registers: before line l is solved, the load of line
+    // l + kXlAhead goes into the slot that line l - 1 used (free by then), so
+    // kXlAhead loads stay in flight behind every solve.  Lanes with no voxels
+    // load from past the buffer and read zeros.
+    auto run = [&](auto full_c) {
+        constexpr int NS = kXlAhead + 1;
+        const int kLines = lpw;
+        int j = row0 % ny, k = row0 / ny;  // the line being solved
+        float rn[NS][K];
+#pragma unroll
+        for (int a = 0; a < kXlAhead; ++a) xl_load<K>(rn[a], rs, line_off(row0 + a, a < kLines && row0 + a < nrows));
+        for (int g = 0; g < kLines; g += NS) {
+#pragma unroll
+            for (int a = 0; a < NS; ++a) {
+                const int row = row0 + g + a;
+                const int nrow = row + kXlAhead;
+                xl_load<K>(rn[(a + kXlAhead) % NS], rs, line_off(nrow, g + a + kXlAhead < kLines && nrow < nrows));
+                if (g + a < kLines && row < nrows) {  // wave-uniform
+                    solve_line(full_c, row, j, k, rn[a]);
+                    if (++j == ny) {
+                        j = 0;
+                        ++k;
+                    }
+                }
+            }
         }
-        if (act) xl_store<K>(o, rs, voff, cnt);
-    }
+    };
+    if (n % K == 0) run(std::true_type{});
+    else run(std::false_type{});
 }
 
-hipError_t launch_sweep_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
-                           float *raw, hipStream_t st)
+hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32,
+                           float *field, float *raw, hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;
-    const dim3 grid(L.total_tiles), block(256);
+    if (lpw < 1 || lpw > kTileLines / 4 || (kTileLines / 4) % lpw != 0) return hipErrorInvalidValue;
+    const long long blocks = (long long)L.total_tiles * ((kTileLines / 4) / lpw);
+    if (blocks >= (1ll << 31)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(256);
     switch (K) {
 #define VL_XL_CASE(k)                                                                                  \
-    case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, subs, xl32, field, raw); break;
+    case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, lpw, subs, xl32, field, raw); break;
         VL_XL_CASE(1)
         VL_XL_CASE(2)
         VL_XL_CASE(4)

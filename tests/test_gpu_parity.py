@@ -122,6 +122,23 @@ def test_fp32_x_lanes_long_lines_100_steps():
     assert_close(got, run_oracle(spec, 100), 1e-5, "x lanes 400")
 
 
+def test_fp32_x_lanes_lines_per_wave():
+    """The x-lines each wave takes (VL_OPT_X_LANE_LINES) change only the
+    launch shape: fields are bitwise equal for every value, on a batch whose
+    volumes have line counts that leave partial tiles and different voxels
+    per lane."""
+    specs = [_spec((200, 13, 7), 2, "mixed", 150, "f32", 501),
+             _spec((300, 5, 3), 1, "dirichlet", 40, "f32", 502),
+             _spec((140, 3, 2), 3, "neumann", 20, "f32", 503)]
+    ref, _ = run_gpu(specs, 8, x_lanes=1, x_lane_lines=16)
+    for k, spec in enumerate(specs):
+        assert_close(ref[k], run_oracle(spec, 8), 1e-5, f"x lanes lpw 16 sim {k}")
+    for lpw in (1, 2, 4, 8):
+        got, _ = run_gpu(specs, 8, x_lanes=1, x_lane_lines=lpw)
+        for k in range(len(specs)):
+            assert np.array_equal(got[k], ref[k]), f"lines per wave {lpw}, sim {k}"
+
+
 def test_fp64_batched_ragged():
     wl = W.batched(n_sims=4, edge_range=(5, 40), cells_range=(20, 300), dtype="f64")
     fields, _ = run_gpu(wl.sims, 10, precision=vb.VL_F64)
@@ -222,20 +239,23 @@ def test_tuner_picks_a_mode_and_caches(tmp_path):
         assert ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_LAUNCHES
         fxy = ctx.get_option(vb.VL_OPT_FUSE_XY)
         xl = ctx.get_option(vb.VL_OPT_X_LANES)
+        lpw = ctx.get_option(vb.VL_OPT_X_LANE_LINES)
         words = open(cache).read().split()
-        assert len(words) == 7 and int(words[3]) == xcd and int(words[4]) == fuse and int(words[5]) == fxy
-        assert int(words[6]) == xl
+        assert len(words) == 8 and int(words[3]) == xcd and int(words[4]) == fuse and int(words[5]) == fxy
+        assert int(words[6]) == xl and int(words[7]) == lpw
         # a second context with the same shapes reads the choice back
         ctx2 = vb.Context(wl.sims)
         ctx2.set_option(vb.VL_OPT_XCD_ORDER, 1 - xcd)
         ctx2.set_option(vb.VL_OPT_FUSE_SOURCES, 1 - fuse)
         ctx2.set_option(vb.VL_OPT_FUSE_XY, 1 - fxy)
+        ctx2.set_option(vb.VL_OPT_X_LANE_LINES, 24 - lpw)  # 16 <-> 8
         ctx2.tune(cache)
         assert ctx2.get_option(vb.VL_OPT_XCD_ORDER) == xcd
         assert ctx2.get_option(vb.VL_OPT_FUSE_SOURCES) == fuse
         assert ctx2.get_option(vb.VL_OPT_FUSE_XY) == fxy
         assert ctx2.get_option(vb.VL_OPT_X_LANES) == xl
-        assert len(open(cache).read().split()) == 7
+        assert ctx2.get_option(vb.VL_OPT_X_LANE_LINES) == lpw
+        assert len(open(cache).read().split()) == 8
         # the tuned context still computes the step correctly
         for k, s in enumerate(wl.sims):
             ctx2.set_field(k, s.rho0)
