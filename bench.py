@@ -270,6 +270,9 @@ def main():
                     help="force the x solve (after tuning): 1 lanes along the line, 0 split solve")
     ap.add_argument("--x-lane-lines", default="auto", choices=["auto", "1", "2", "4", "8", "16"],
                     help="force the x-lines per wave of the lanes-along-the-line solve (after tuning)")
+    ap.add_argument("--sources", default="auto", choices=["auto", "0", "1", "2"],
+                    help="force where cell sources are applied (after tuning): 0 own kernel, 1 in the z sweep, "
+                         "2 carried into the next x solve")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
@@ -299,8 +302,11 @@ def main():
         ctx.set_option(vb.VL_OPT_X_LANES, int(args.x_lanes))
     if args.x_lane_lines != "auto" and precision == vb.VL_F32:
         ctx.set_option(vb.VL_OPT_X_LANE_LINES, int(args.x_lane_lines))
+    if args.sources != "auto" and precision == vb.VL_F32:
+        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, int(args.sources))
     mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
-    fuse_src = bool(ctx.get_option(vb.VL_OPT_FUSE_SOURCES))
+    fuse_src = {0: "own kernel", 1: "in the z sweep", 2: "carried into the next x solve"}[
+        ctx.get_option(vb.VL_OPT_FUSE_SOURCES)] if precision == vb.VL_F32 else "own kernel"
     xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))
     x_lanes = bool(ctx.get_option(vb.VL_OPT_X_LANES)) if precision == vb.VL_F32 else False
     x_lane_lines = ctx.get_option(vb.VL_OPT_X_LANE_LINES) if x_lanes else None
@@ -378,7 +384,7 @@ def main():
                    "grid": list(wl.sims[0].shape) if len(wl.sims) == 1 else "ragged",
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
                    "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode,
-                   "xy_per_plane": fused_xy, "fuse_sources": fuse_src, "xcd_order": xcd_ord,
+                   "xy_per_plane": fused_xy, "cell_sources": fuse_src, "xcd_order": xcd_ord,
                    "x_lanes_along_line": x_lanes, "x_lines_per_wave": x_lane_lines},
         "hbm_effective": {"basis": "B_alg: three sweeps x (read + write) per voxel-substrate-step; with x and y "
                                    "solved per z-plane the step moves less than B_alg",

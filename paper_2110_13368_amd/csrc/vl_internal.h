@@ -93,6 +93,9 @@ struct SimCells {
     int comp_base;   // first float2 of the FP32 composites (n_occ x ns)
     int ab_base;     // first double2 of the sorted per-cell (a, b) (n_cells x ns)
     int zl_base;     // first entry of the z-line starts (nx*ny + 1), -1 without cells
+    int xs_base;     // first entry of the x-line starts (ny*nz + 1) when this simulation's sources
+                     // can be carried into the next x solve (FP32, x-lines solved with the lanes
+                     // along the line, cells present), else -1
 };
 
 // Cell sources applied by the z sweep after its stores (FP32 path).  The
@@ -103,6 +106,19 @@ struct FusedSources {
     const int *line_start;
     const int *occ_vox;
     const float2 *comp;
+    int enabled;
+    int skip_carried;  // leave simulations with xs_base >= 0 to the next x solve
+};
+
+// Cell sources of the previous step applied by the x solve (lanes along the
+// line) to each line as it is loaded, before the Dirichlet projection: the
+// occupied voxels in voxel order, each x-line's first entry (xs_base), their
+// FP32 composites in the same order.
+struct CarriedSources {
+    const SimCells *cells;
+    const int *xline_start;
+    const int *occ_vox_v;
+    const float2 *comp_v;
     int enabled;
 };
 
@@ -138,7 +154,7 @@ hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev 
 hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *coef_unused, float *xl32,
                             hipStream_t st);
 hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
-                           float *raw, hipStream_t st);
+                           float *raw, const CarriedSources &carry, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
 // raw (may be null, same layout as the field) receives each solve's output
@@ -196,8 +212,10 @@ hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start,
                              int n_occ, int ns, const double *V, const double *S,
                              const double *U, const double *RS, double dt, double vvox,
-                             const int *pos, float2 *comp32, double2 *ab64, double *krs,
-                             double *kcell, int *cell_of, hipStream_t st);
+                             const int *pos, float2 *comp32, float2 *comp32_v, double2 *ab64,
+                             double *krs, double *kcell, int *cell_of, hipStream_t st);
+hipError_t launch_xline_starts(const int *occ_vox_v, int n_occ, int nx, int nlines, int *line_start,
+                               hipStream_t st);
 hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
                               unsigned long long *zkeys, int *occ_vox, int *pos, int *line_start,
                               hipStream_t st);
@@ -206,7 +224,7 @@ hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix,
                               int total_occ, int max_ns, const SubDev *subs,
                               const int *occ_vox, const float2 *comp, float *field,
-                              hipStream_t st);
+                              int only_carried, hipStream_t st);
 hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ_prefix,
                                 int total_occ, const SubDev *subs, const int *occ_vox,
                                 const int *seg_start, const double2 *ab, double *field,

@@ -446,9 +446,9 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
                                   const double *__restrict__ V, const double *__restrict__ S,
                                   const double *__restrict__ U, const double *__restrict__ RS,
                                   double dt, double vvox, const int *__restrict__ pos,
-                                  float2 *__restrict__ comp32, double2 *__restrict__ ab64,
-                                  double *__restrict__ krs, double *__restrict__ kcell,
-                                  int *__restrict__ cell_of)
+                                  float2 *__restrict__ comp32, float2 *__restrict__ comp32_v,
+                                  double2 *__restrict__ ab64, double *__restrict__ krs,
+                                  double *__restrict__ kcell, int *__restrict__ cell_of)
 {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)n_occ * ns) return;
@@ -468,18 +468,49 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
         A = A + a * B;
         B = B * b;
     }
-    if (comp32) comp32[(size_t)out * ns + s] = make_float2((float)A, (float)(1.0 / B));
+    const float2 c32 = make_float2((float)A, (float)(1.0 / B));
+    if (comp32) comp32[(size_t)out * ns + s] = c32;
+    if (comp32_v) comp32_v[(size_t)seg * ns + s] = c32;
 }
 
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, int n_occ, int ns,
                              const double *V, const double *S, const double *U, const double *RS,
-                             double dt, double vvox, const int *pos, float2 *comp32, double2 *ab64,
-                             double *krs, double *kcell, int *cell_of, hipStream_t st)
+                             double dt, double vvox, const int *pos, float2 *comp32, float2 *comp32_v,
+                             double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st)
 {
     const long long total = (long long)n_occ * ns;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(composites_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys,
-                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, ab64, krs, kcell, cell_of);
+                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, comp32_v, ab64, krs, kcell,
+                       cell_of);
+    return hipGetLastError();
+}
+
+// First entry of every x-line (j + ny k) in the occupied voxels listed in
+// voxel order: the lower bound of the line's first voxel index.
+__global__ void xline_starts_kernel(const int *__restrict__ occ_vox_v, int n_occ, int nx, int nlines,
+                                    int *__restrict__ line_start)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > nlines) return;
+    const long long v0 = (long long)l * nx;
+    int lo = 0, hi = n_occ;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)occ_vox_v[mid] < v0)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    line_start[l] = lo;
+}
+
+hipError_t launch_xline_starts(const int *occ_vox_v, int n_occ, int nx, int nlines, int *line_start,
+                               hipStream_t st)
+{
+    if (nlines < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(xline_starts_kernel, dim3((nlines + 1 + 255) / 256), dim3(256), 0, st, occ_vox_v, n_occ,
+                       nx, nlines, line_start);
     return hipGetLastError();
 }
 
@@ -503,14 +534,14 @@ __device__ __forceinline__ int find_slot_i(const int *__restrict__ prefix, int c
 __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims,
                                    const int *__restrict__ occ_prefix, int total_occ,
                                    const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
-                                   const float2 *__restrict__ comp, float *__restrict__ field)
+                                   const float2 *__restrict__ comp, float *__restrict__ field, int only_carried)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (j >= total_occ) return;
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
-    if (s >= C.ns) return;
+    if (s >= C.ns || (only_carried && C.xs_base < 0)) return;
     const int jl = j - occ_prefix[sim];
     const int v = occ_vox[C.occ_base + jl];
     const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
@@ -520,11 +551,11 @@ __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims
 
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
                               int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
-                              float *field, hipStream_t st)
+                              float *field, int only_carried, hipStream_t st)
 {
     if (total_occ <= 0) return hipSuccess;
     hipLaunchKernelGGL(sources_f32_kernel, dim3((total_occ + 255) / 256, max_ns), dim3(256), 0, st,
-                       cells, nsims, occ_prefix, total_occ, subs, occ_vox, comp, field);
+                       cells, nsims, occ_prefix, total_occ, subs, occ_vox, comp, field, only_carried);
     return hipGetLastError();
 }
 

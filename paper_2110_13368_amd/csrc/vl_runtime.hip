@@ -59,6 +59,7 @@ struct SimHost {
     int sub0 = 0;
     // cell tables
     int occ_base = 0, comp_base = 0, ab_base = 0, zl_base = -1;
+    int xs_base = -1;  // x-line starts of the carried sources, -1 when not eligible
     int n_cells = 0, n_occ = 0, n_out = 0;
     long long nvox() const { return (long long)n[0] * n[1] * n[2]; }
 };
@@ -104,7 +105,10 @@ struct vl_ctx {
     int stage_ns = 0;      // max over sims of ns
     int key_pad = 0;       // next_pow2(stage_cells)
     int zl_total = 0;      // sum over sims with cells of (nx*ny + 1)
-    bool fuse_sources = true;
+    int xs_total = 0;      // sum over sims eligible for carried sources of (ny*nz + 1)
+    // cell sources: 0 separate kernel, 1 fused into the z sweep, 2 carried
+    // into the next step's x solve where eligible (z sweep for the others)
+    int fuse_sources = 1;
     // x and y solved together per z-plane where the plane fits in LDS: the
     // launches of that mode (planes, and x / y of the other volumes)
     bool fuse_xy = false;
@@ -137,14 +141,17 @@ struct vl_ctx {
     size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
     size_t o_zkeys = 0, o_occ_tmp = 0, o_pos_idx = 0, o_line_start = 0;
     size_t o_krs = 0, o_kcell = 0, o_cell_of = 0, o_occ_vox_v = 0;
+    size_t o_xline_start = 0, o_comp_v = 0;
     size_t n_coef32 = 0, n_coef64 = 0;
 
     char *ws = nullptr;
     void *field = nullptr;
     hipStream_t stream = nullptr;
 
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // captured steps: [0] a whole step; with carried sources [1] the first
+    // step of a call, [2] the following steps, [3] the closing sources pass
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
     bool graph_valid = false;
 
     bool profiling = false;
@@ -174,10 +181,12 @@ int check_sim(vl_ctx *ctx, int sim)
 
 void drop_graph(vl_ctx *ctx)
 {
-    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
-    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-    ctx->exec = nullptr;
-    ctx->graph = nullptr;
+    for (int g = 0; g < 4; ++g) {
+        if (ctx->exec[g]) (void)hipGraphExecDestroy(ctx->exec[g]);
+        if (ctx->graph[g]) (void)hipGraphDestroy(ctx->graph[g]);
+        ctx->exec[g] = nullptr;
+        ctx->graph[g] = nullptr;
+    }
     ctx->graph_valid = false;
 }
 
@@ -244,7 +253,23 @@ int timed(vl_ctx *ctx, int kind, F &&launch)
 
 // ---- one step ------------------------------------------------------------
 
-int enqueue_step(vl_ctx *ctx)
+// Whether the steps of this context carry the cell sources of eligible
+// simulations into the next step's x solve (VL_OPT_FUSE_SOURCES 2).
+bool carries(const vl_ctx *ctx)
+{
+    if (ctx->precision != VL_F32 || ctx->fuse_sources != 2 || !ctx->x_lanes) return false;
+    if (ctx->step_mode != VL_MODE_LAUNCHES || (ctx->fuse_xy && ctx->xy_ready)) return false;
+    for (const SimHost &s : ctx->sims)
+        if (s.xs_base >= 0 && s.n_occ > 0) return true;
+    return false;
+}
+
+// phase: kStepWhole a complete step; with carried sources kStepCarryFirst
+// (the z sweep leaves eligible simulations' sources to the next x solve) and
+// kStepCarry (the x solve also applies the previous step's).
+enum { kStepWhole = 0, kStepCarryFirst = 1, kStepCarry = 2 };
+
+int enqueue_step(vl_ctx *ctx, int phase)
 {
     hipStream_t st = ctx->stream;
     const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
@@ -255,9 +280,13 @@ int enqueue_step(vl_ctx *ctx)
     if (ctx->precision == VL_F32) {
         float *field = (float *)ctx->field;
         const float2 *coef = ctx->at<float2>(ctx->o_coef32);
-        const bool fused = ctx->fuse_sources && total_occ > 0;
+        const bool fused = ctx->fuse_sources >= 1 && total_occ > 0;
         const vl::FusedSources src{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
-                                   ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), fused ? 1 : 0};
+                                   ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), fused ? 1 : 0,
+                                   phase != kStepWhole ? 1 : 0};
+        const vl::CarriedSources carry{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_xline_start),
+                                       ctx->at<int>(ctx->o_occ_vox_v), ctx->at<float2>(ctx->o_comp_v),
+                                       phase == kStepCarry ? 1 : 0};
         if (ctx->step_mode == VL_MODE_PERSISTENT) {
             const int *it = ctx->at<int>(ctx->o_itable);
             int dev = 0, khz = 100000;
@@ -304,7 +333,7 @@ int enqueue_step(vl_ctx *ctx)
                                       ctx->xcd_order ? 1 : 0};
                     rc = timed(ctx, VL_K_SWEEP_X, [&] {
                         return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<float>(ctx->o_xl32),
-                                                   field, nullptr, st);
+                                                   field, nullptr, carry, st);
                     });
                     if (rc) return rc;
                 }
@@ -327,7 +356,7 @@ int enqueue_step(vl_ctx *ctx)
                 return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
                                               ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
                                               subs, ctx->at<int>(ctx->o_occ_vox),
-                                              ctx->at<float2>(ctx->o_comp), field, st);
+                                              ctx->at<float2>(ctx->o_comp), field, 0, st);
             });
             if (rc) return rc;
         }
@@ -375,13 +404,29 @@ int enqueue_step(vl_ctx *ctx)
     return VL_OK;
 }
 
+// The sources of the last step of a call with carried sources: the
+// standalone kernel over the simulations whose sources were carried.
+int enqueue_carried_sources(vl_ctx *ctx)
+{
+    int total_occ = 0;
+    for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+    return timed(ctx, VL_K_SOURCES, [&] {
+        return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
+                                      ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
+                                      ctx->at<SubDev>(ctx->o_subs), ctx->at<int>(ctx->o_occ_vox),
+                                      ctx->at<float2>(ctx->o_comp), (float *)ctx->field, 1, ctx->stream);
+    });
+}
+
 int upload_cell_tables(vl_ctx *ctx)
 {
     std::vector<vl::SimCells> cells(ctx->n_sims);
     std::vector<int> prefix(ctx->n_sims + 1, 0);
     for (int k = 0; k < ctx->n_sims; ++k) {
         const SimHost &s = ctx->sims[k];
-        cells[k] = vl::SimCells{s.sub0, s.ns, s.n_occ, s.occ_base, s.occ_base, s.comp_base, s.ab_base, s.zl_base};
+        cells[k] = vl::SimCells{s.sub0,       s.ns,      s.n_occ,   s.occ_base,
+                                s.occ_base,   s.comp_base, s.ab_base, s.zl_base,
+                                s.n_occ > 0 ? s.xs_base : -1};
         prefix[k + 1] = prefix[k] + s.n_occ;
     }
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_cells, cells.data(), cells.size() * sizeof(vl::SimCells),
@@ -808,14 +853,21 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->stage_cells = 0;
     ctx->stage_ns = 0;
     ctx->zl_total = 0;
+    ctx->xs_total = 0;
     for (SimHost &s : ctx->sims) {
         s.occ_base = ctx->cap_total;
         s.comp_base = ctx->comp_total;
         s.ab_base = ctx->comp_total;
         s.zl_base = -1;
+        s.xs_base = -1;
         if (s.max_cells > 0 && ctx->precision == VL_F32) {
             s.zl_base = ctx->zl_total;
             ctx->zl_total += s.n[0] * s.n[1] + 1;
+            // sources can ride on the x solve with lanes along the line
+            if (s.n[0] >= vl::kXLaneMinN && s.n[0] <= 64 * vl::kXLaneMaxK) {
+                s.xs_base = ctx->xs_total;
+                ctx->xs_total += s.n[1] * s.n[2] + 1;
+            }
         }
         ctx->cap_total += s.max_cells + 1;
         ctx->comp_total += s.max_cells * s.ns;
@@ -867,6 +919,8 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_occ_tmp = take(zorder ? sizeof(int) * (ctx->stage_cells + 1) : 0);
     ctx->o_pos_idx = take(zorder ? sizeof(int) * ctx->stage_cells : 0);
     ctx->o_line_start = take(sizeof(int) * ctx->zl_total);
+    ctx->o_xline_start = take(sizeof(int) * ctx->xs_total);
+    ctx->o_comp_v = take(zorder ? sizeof(float2) * ctx->comp_total : 0);
     ctx->o_qcounters = take(sizeof(unsigned) * (2 + 3 * (size_t)nsubs));
     ctx->o_qerror = take(sizeof(int));
     ctx->ws_bytes = w;
@@ -1097,12 +1151,16 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
                                           ctx->at<unsigned long long>(ctx->o_zkeys),
                                           ctx->at<int>(ctx->o_occ_vox) + s.occ_base, pos,
                                           ctx->at<int>(ctx->o_line_start) + s.zl_base, st));
+            if (s.xs_base >= 0)
+                VL_HIP(vl::launch_xline_starts(occ_v, n_occ, s.n[0], s.n[1] * s.n[2],
+                                               ctx->at<int>(ctx->o_xline_start) + s.xs_base, st));
         }
         const double vvox = s.h[0] * s.h[1] * s.h[2];
         VL_HIP(vl::launch_composites(keys, ctx->at<int>(ctx->o_seg_start) + s.occ_base, n_occ, s.ns,
                                      ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S),
                                      ctx->at<double>(ctx->o_U), ctx->at<double>(ctx->o_RS), ctx->dt, vvox,
                                      pos, zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
+                                     zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr,
                                      ctx->at<double2>(ctx->o_ab) + s.ab_base,
                                      zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
                                      zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
@@ -1120,28 +1178,50 @@ int vl_step(vl_ctx *ctx, int n_steps)
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (n_steps < 0) return fail(VL_E_ARG, "n_steps must be >= 0");
     if (n_steps == 0) return VL_OK;
+    // With carried sources a call is: the first step, the following steps,
+    // then the last step's sources, so that the field is whole on return.
+    const bool carry = carries(ctx);
     if (ctx->profiling || ctx->stream == nullptr) {
         for (int t = 0; t < n_steps; ++t)
-            if (int rc = enqueue_step(ctx)) return rc;
+            if (int rc = enqueue_step(ctx, carry ? (t == 0 ? kStepCarryFirst : kStepCarry) : kStepWhole)) return rc;
+        if (carry)
+            if (int rc = enqueue_carried_sources(ctx)) return rc;
         if (ctx->recs.size() > 200000) return collect_events(ctx);
         return VL_OK;
     }
     if (!ctx->graph_valid) {
         drop_graph(ctx);
-        VL_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_step(ctx);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+        auto capture = [&](int g, int what) -> int {
+            VL_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            const int rc = what < 0 ? enqueue_carried_sources(ctx) : enqueue_step(ctx, what);
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
+            if (rc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return fail(VL_E_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+            ctx->graph[g] = gr;
+            VL_HIP(hipGraphInstantiate(&ctx->exec[g], gr, nullptr, nullptr, 0));
+            return VL_OK;
+        };
+        if (!carry) {
+            if (int rc = capture(0, kStepWhole)) return rc;
+        } else {
+            if (int rc = capture(1, kStepCarryFirst)) return rc;
+            if (int rc = capture(2, kStepCarry)) return rc;
+            if (int rc = capture(3, -1)) return rc;
         }
-        if (e != hipSuccess) return fail(VL_E_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
-        ctx->graph = g;
-        VL_HIP(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
         ctx->graph_valid = true;
     }
-    for (int t = 0; t < n_steps; ++t) VL_HIP(hipGraphLaunch(ctx->exec, ctx->stream));
+    if (!carry) {
+        for (int t = 0; t < n_steps; ++t) VL_HIP(hipGraphLaunch(ctx->exec[0], ctx->stream));
+        return VL_OK;
+    }
+    VL_HIP(hipGraphLaunch(ctx->exec[1], ctx->stream));
+    for (int t = 1; t < n_steps; ++t) VL_HIP(hipGraphLaunch(ctx->exec[2], ctx->stream));
+    VL_HIP(hipGraphLaunch(ctx->exec[3], ctx->stream));
     return VL_OK;
 }
 
@@ -1197,9 +1277,9 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
 {
     if (int rc = check_ctx(ctx)) return rc;
     if (option == VL_OPT_FUSE_SOURCES) {
-        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_FUSE_SOURCES takes 0 or 1");
-        if (ctx->fuse_sources != (value == 1)) drop_graph(ctx);
-        ctx->fuse_sources = value == 1;
+        if (value < 0 || value > 2) return fail(VL_E_ARG, "VL_OPT_FUSE_SOURCES takes 0, 1 or 2");
+        if (ctx->fuse_sources != value) drop_graph(ctx);
+        ctx->fuse_sources = value;
         return VL_OK;
     }
     if (option == VL_OPT_STEP_MODE) {
@@ -1259,7 +1339,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     if (int rc = check_ctx(ctx)) return rc;
     if (!value) return fail(VL_E_ARG, "value is null");
     switch (option) {
-    case VL_OPT_FUSE_SOURCES: *value = ctx->fuse_sources ? 1 : 0; return VL_OK;
+    case VL_OPT_FUSE_SOURCES: *value = ctx->fuse_sources; return VL_OK;
     case VL_OPT_STEP_MODE: *value = ctx->step_mode; return VL_OK;
     case VL_OPT_PERSISTENT_GRID: *value = ctx->persistent_grid; return VL_OK;
     case VL_OPT_WAIT_LIMIT_US: *value = ctx->wait_limit_us; return VL_OK;
@@ -1334,7 +1414,7 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     for (int xy = any_plane ? 1 : 0; xy >= 0; --xy)
         for (int xl = xy ? 0 : 1; xl >= 0; --xl)
             for (int xcd = 1; xcd >= 0; --xcd)
-                for (int fuse = 1; fuse >= 0; --fuse) {
+                for (int fuse = xl ? 2 : 1; fuse >= 0; --fuse) {
                     cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, kDefaultXLaneLines});
                     if (xl && xcd) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, 16});
                 }
@@ -1483,7 +1563,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
     const float2 *coef = ctx->at<float2>(ctx->o_coef32);
     float *field = (float *)ctx->field;
     const vl::FusedSources nosrc{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
-                                 ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0};
+                                 ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0, 0};
     // x: the lanes-along-the-line solve for long lines when selected, the
     // split sweeps otherwise; then y and z
     std::vector<std::pair<const Launch *, bool>> order;  // (launch, lanes along the line)
@@ -1504,8 +1584,9 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
                           L.count, L.total_tiles, 1};
         if (o.second) {
             if (int rc = timed(ctx, VL_K_REPLAY_X, [&] {
+                    const vl::CarriedSources none{nullptr, nullptr, nullptr, nullptr, 0};
                     return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<float>(ctx->o_xl32), field,
-                                               (float *)(aws + A.raw[0]), st);
+                                               (float *)(aws + A.raw[0]), none, st);
                 }))
                 return rc;
             continue;
@@ -1547,7 +1628,7 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
     for (int t = 0; t < n_steps; ++t) {
         if (t % K == 0)
             if (int r = copy(aws + A.ck + F * (t / K), ctx->field)) return r;
-        if (int r = enqueue_step(ctx)) return r;
+        if (int r = enqueue_step(ctx, kStepWhole)) return r;
         if (int r = drain()) return r;
     }
     if (n_steps == 0)
@@ -1573,7 +1654,7 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
         for (int t = t0; t < t1; ++t) {
             if (int r = copy(aws + A.seg + F * (t - t0), ctx->field)) return r;
             if (t + 1 < t1)
-                if (int r = enqueue_step(ctx)) return r;
+                if (int r = enqueue_step(ctx, kStepWhole)) return r;
         }
         for (int t = t1 - 1; t >= t0; --t) {
             if (int r = copy(ctx->field, aws + A.seg + F * (t - t0))) return r;

@@ -300,7 +300,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
         // ---- cell sources of this tile's z-lines (after the last P_D) ----
         if (AXIS == 2 && src.enabled) {
             const SimCells &C = src.cells[S.sim];
-            if (C.zl_base >= 0) {
+            if (C.zl_base >= 0 && !(src.skip_carried && C.xs_base >= 0)) {
                 const int nlines = nx * ny;
                 const int L0 = local * kTileLines;
                 const int *ls = src.line_start + C.zl_base;

@@ -212,8 +212,12 @@ constexpr int kXlAhead = 2;
 template <int K>
 __global__ void __launch_bounds__(256)
 sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *__restrict__ xl32,
-         float *__restrict__ field, float *__restrict__ raw)
+         float *__restrict__ field, float *__restrict__ raw, CarriedSources carry)
 {
+    // per wave: which of a lane's voxels receive a carried source, and the
+    // composites by voxel of the line
+    __shared__ unsigned cs_mask[4][64];
+    __shared__ float2 cs_ab[4][64 * K];
     constexpr int KM = K > 1 ? K - 1 : 1;
     const int parts = (kTileLines / 4) / lpw;  // workgroups per tile
     const int blk = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -293,15 +297,60 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     auto from_lane = [](int addr, float x) {
         return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
     };
+    // cell sources of the previous step carried into this solve (uniform)
+    const SimCells *CC = carry.enabled ? &carry.cells[S.sim] : nullptr;
+    const bool carried = CC != nullptr && CC->xs_base >= 0;
+    const int *__restrict__ xs = carried ? carry.xline_start + CC->xs_base : nullptr;
+    const int *__restrict__ ov = carried ? carry.occ_vox_v + CC->occ_base : nullptr;
+    const float2 *__restrict__ cab = carried ? carry.comp_v + CC->comp_base + S.sub : nullptr;
+    const int cns = carried ? CC->ns : 0;
+    // rho <- (rho + A) * (1/B) on the occupied voxels of line `row`, entries
+    // [e0, e1) of the voxel-ordered list, 64 at a time: each entry's lane
+    // writes its composite to the wave's LDS slot of that voxel and marks the
+    // voxel in its owner lane's mask; owners then update their registers.
+    auto carry_in = [&](const int row, float (&r)[K]) {
+        const int e0 = xs[row], e1 = xs[row + 1];
+        for (int c0 = e0; c0 < e1; c0 += 64) {  // uniform
+            const int e = c0 + lane;
+            const bool ok = e < e1;
+            int i = 0;
+            float2 ab = make_float2(0.f, 1.f);
+            if (ok) {
+                i = ov[e] - row * nx;
+                ab = cab[(size_t)e * cns];
+            }
+            // Lanes talk through LDS here: the wavefront-scope fences keep
+            // the compiler from moving these accesses across the phases (or
+            // forwarding a lane's own cleared mask to its read); the wave's
+            // LDS operations themselves execute in order.
+            cs_mask[wave][lane] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (ok) {
+                atomicOr(&cs_mask[wave][i / K], 1u << (i % K));
+                cs_ab[wave][i] = ab;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const unsigned mk = cs_mask[wave][lane];
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (mk & (1u << t)) {
+                    const float2 q = cs_ab[wave][K * lane + t];
+                    r[t] = (r[t] + q.x) * q.y;
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    };
+
     // faces of the first and last voxel of a line on no y/z Dirichlet face
     const int f_first0 = max(lo_f, n == 1 ? hi_f : -1), f_last0 = hi_f;
     const float v_first0 = fval(f_first0), v_last0 = fval(f_last0);
 
     // One line.  With FULL (n a multiple of K) every active lane holds K
     // voxels, so the per-lane interval length is the constant K - 1.
-    auto solve_line = [&](auto full_c, const int row, const int j, const int k, float (&r)[K]) {
+    auto solve_line = [&](auto full_c, auto carry_c, const int row, const int j, const int k, float (&r)[K]) {
         constexpr bool FULL = decltype(full_c)::value;
         const int mm = FULL ? K - 1 : m;
+        if (decltype(carry_c)::value) carry_in(row, r);
         // Dirichlet projection before the solve: the end voxels of the line
         r[0] = set_in_lo ? v_in_lo : r[0];
 #pragma unroll
@@ -387,7 +436,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     // l + kXlAhead goes into the slot that line l - 1 used (free by then), so
     // kXlAhead loads stay in flight behind every solve.  Lanes with no voxels
     // load from past the buffer and read zeros.
-    auto run = [&](auto full_c) {
+    auto run = [&](auto full_c, auto carry_c) {
         constexpr int NS = kXlAhead + 1;
         const int kLines = lpw;
         int j = row0 % ny, k = row0 / ny;  // the line being solved
@@ -401,7 +450,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
                 const int nrow = row + kXlAhead;
                 xl_load<K>(rn[(a + kXlAhead) % NS], rs, line_off(nrow, g + a + kXlAhead < kLines && nrow < nrows));
                 if (g + a < kLines && row < nrows) {  // wave-uniform
-                    solve_line(full_c, row, j, k, rn[a]);
+                    solve_line(full_c, carry_c, row, j, k, rn[a]);
                     if (++j == ny) {
                         j = 0;
                         ++k;
@@ -410,12 +459,17 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
             }
         }
     };
-    if (n % K == 0) run(std::true_type{});
-    else run(std::false_type{});
+    if (carried) {
+        if (n % K == 0) run(std::true_type{}, std::true_type{});
+        else run(std::false_type{}, std::true_type{});
+    } else {
+        if (n % K == 0) run(std::true_type{}, std::false_type{});
+        else run(std::false_type{}, std::false_type{});
+    }
 }
 
 hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32,
-                           float *field, float *raw, hipStream_t st)
+                           float *field, float *raw, const CarriedSources &carry, hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;
     if (lpw < 1 || lpw > kTileLines / 4 || (kTileLines / 4) % lpw != 0) return hipErrorInvalidValue;
@@ -424,7 +478,7 @@ hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *s
     const dim3 grid((unsigned)blocks), block(256);
     switch (K) {
 #define VL_XL_CASE(k)                                                                                  \
-    case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, lpw, subs, xl32, field, raw); break;
+    case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, lpw, subs, xl32, field, raw, carry); break;
         VL_XL_CASE(1)
         VL_XL_CASE(2)
         VL_XL_CASE(4)

@@ -11,11 +11,13 @@ from paper_2110_13368_amd import binding as vb
 
 
 def run_gpu(specs, steps, precision=vb.VL_F32, decay=vb.VL_DECAY_ONCE, profiling=False, fuse=True, x_lanes=0,
-            x_lane_lines=None):
+            x_lane_lines=None, sources_mode=None):
     ctx = vb.Context(specs, precision=precision, decay_split=decay, device="cuda:0")
     try:
         if not fuse:
             vb.vl_set_option(ctx.h, vb.VL_OPT_FUSE_SOURCES, 0)
+        if sources_mode is not None:
+            vb.vl_set_option(ctx.h, vb.VL_OPT_FUSE_SOURCES, sources_mode)
         if precision == vb.VL_F32:
             vb.vl_set_option(ctx.h, vb.VL_OPT_X_LANES, x_lanes)
             if x_lane_lines is not None:

@@ -123,7 +123,10 @@ def test_options_on_the_host():
             assert _code(vb.vl_set_option, h, vb.VL_OPT_X_LANE_LINES, v) == vb.VL_E_ARG
         vb.vl_set_option(h, vb.VL_OPT_XCD_ORDER, 0)
         assert vb.vl_get_option(h, vb.VL_OPT_XCD_ORDER) == 0
-        assert _code(vb.vl_set_option, h, vb.VL_OPT_FUSE_SOURCES, 2) == vb.VL_E_ARG
+        vb.vl_set_option(h, vb.VL_OPT_FUSE_SOURCES, 2)  # carried into the next x solve
+        assert vb.vl_get_option(h, vb.VL_OPT_FUSE_SOURCES) == 2
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_FUSE_SOURCES, 3) == vb.VL_E_ARG
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_FUSE_SOURCES, -1) == vb.VL_E_ARG
         assert _code(vb.vl_set_option, h, 99, 0) == vb.VL_E_ARG
         # the one-launch step is switched off for now and says so
         assert _code(vb.vl_set_option, h, vb.VL_OPT_STEP_MODE, vb.VL_MODE_PERSISTENT) == vb.VL_E_STATE

@@ -1,0 +1,120 @@
+"""Cell sources carried into the next step's x solve (VL_OPT_FUSE_SOURCES 2).
+
+The step is rho <- C P_D S_z P_D S_y P_D F S_x P_D (rho) (Eq. 1 solved by
+LOD, the sources applied after the diffusion-decay solve).  With mode 2 the
+source update C of a step is applied to each x-line as the next step's x
+solve loads it, ahead of that step's first Dirichlet projection, and one
+standalone pass applies the last step's sources before the call returns.
+The arithmetic per voxel is the same FP32 update in the same order as the
+source update fused into the z sweep (mode 1) or run as its own kernel
+(mode 0), so the three modes must give bitwise equal fields; all are also
+checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2110_13368_amd import binding as vb
+from paper_2110_13368_amd import workloads as W
+from tests.gpu_helpers import assert_close, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _spec(shape, n_sub, bc, n_cells, seed, layout="uniform"):
+    rng = np.random.default_rng(W.SEED_BASE + 900 + seed)
+    h = (20.0, 20.0, 20.0)
+    return W.make_sim(rng, shape, h, n_sub, dtype="f32", bc=bc, n_cells=n_cells, cell_layout=layout,
+                      sigma=0.25 * min(n * d for n, d in zip(shape, h)))
+
+
+def _line_cells(spec, lines, seed):
+    """Replace the cells by cells on every voxel of some x-lines (j, k, count),
+    two cells in some voxels, plus the original cells."""
+    rng = np.random.default_rng(seed)
+    nx = spec.shape[0]
+    pos = []
+    for (j, k, cnt) in lines:
+        for i in rng.choice(nx, size=cnt, replace=False):
+            c = [spec.lo[0] + (i + 0.5) * spec.h[0], spec.lo[1] + (j + 0.5) * spec.h[1],
+                 spec.lo[2] + (k + 0.5) * spec.h[2]]
+            pos.append(c)
+            if i % 7 == 0:
+                pos.append(c)
+    pos = np.concatenate([np.array(pos), spec.cells.pos], axis=0)
+    n, ns = pos.shape[0], spec.n_sub
+    spec.cells = W.Cells(pos=pos, V=rng.uniform(1000.0, 4000.0, n),
+                         S=10 ** rng.uniform(-1, 1, (n, ns)), U=10 ** rng.uniform(-1, 1, (n, ns)),
+                         rho_star=rng.uniform(0.0, 40.0, (n, ns)))
+    return spec
+
+
+def _batch():
+    # eligible (x-lines of 129+ voxels, cells), eligible without cells, not
+    # eligible (short x-lines), and one with x-lines holding more than 64
+    # occupied voxels
+    a = _spec((150, 9, 7), 2, "mixed", 400, 1, layout="gaussian")
+    b = _spec((131, 5, 4), 1, "dirichlet", 0, 2)
+    c = _spec((60, 17, 11), 2, "mixed", 300, 3)
+    d = _line_cells(_spec((200, 6, 5), 3, "neumann", 100, 4), [(2, 3, 200), (0, 0, 70), (5, 4, 64), (1, 2, 65)], 41)
+    e = _spec((257, 3, 4), 1, "mixed", 200, 5)
+    return [a, b, c, d, e]
+
+
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_carried_sources_equal_other_modes(steps):
+    specs = _batch()
+    f2, n2 = run_gpu(specs, steps, x_lanes=1, sources_mode=2)
+    f1, n1 = run_gpu(specs, steps, x_lanes=1, sources_mode=1)
+    f0, _ = run_gpu(specs, steps, x_lanes=1, sources_mode=0)
+    assert n1 == n2
+    for k in range(len(specs)):
+        assert np.array_equal(f2[k], f1[k]), f"sim {k}: carried vs fused into z"
+        assert np.array_equal(f2[k], f0[k]), f"sim {k}: carried vs separate kernel"
+        assert_close(f2[k], run_oracle(specs[k], steps), 1e-5, f"carried sim {k}")
+
+
+def test_carried_sources_without_graphs():
+    # with kernel timing on, steps are launched one by one instead of replayed
+    specs = _batch()[:2] + _batch()[3:4]
+    a, _ = run_gpu(specs, 4, x_lanes=1, sources_mode=2, profiling=True)
+    b, _ = run_gpu(specs, 4, x_lanes=1, sources_mode=1)
+    for k in range(len(specs)):
+        assert np.array_equal(a[k], b[k]), f"sim {k}"
+
+
+def test_carried_sources_across_calls_and_new_cells():
+    specs = _batch()
+    out = {}
+    for mode in (2, 1):
+        ctx = vb.Context(specs, device="cuda:0")
+        try:
+            ctx.set_option(vb.VL_OPT_X_LANES, 1)
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, mode)
+            for k, s in enumerate(specs):
+                ctx.set_field(k, s.rho0)
+            ctx.step(2)
+            m = [ctx.mass(k) for k in range(len(specs))]
+            ctx.step(1)
+            # move the cells of the first simulation, then go on stepping
+            c = specs[0].cells
+            ctx.upload_cells(0, W.Cells(pos=c.pos[::-1].copy() + 7.0, V=c.V, S=c.S, U=c.U, rho_star=c.rho_star))
+            ctx.step(3)
+            ctx.sync()
+            out[mode] = ([ctx.get_field(k) for k in range(len(specs))], m)
+        finally:
+            ctx.close()
+    for k in range(len(specs)):
+        assert np.array_equal(out[2][0][k], out[1][0][k]), f"sim {k}"
+        assert np.array_equal(np.asarray(out[2][1][k]), np.asarray(out[1][1][k])), f"mass sim {k}"
+
+
+def test_carried_sources_option_values():
+    ctx = vb.Context(_batch()[:1], device="cuda:0")
+    try:
+        for v in (0, 1, 2):
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, v)
+            assert ctx.get_option(vb.VL_OPT_FUSE_SOURCES) == v
+        with pytest.raises(Exception):
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, 3)
+    finally:
+        ctx.close()

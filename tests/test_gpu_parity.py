@@ -246,7 +246,7 @@ def test_tuner_picks_a_mode_and_caches(tmp_path):
         # a second context with the same shapes reads the choice back
         ctx2 = vb.Context(wl.sims)
         ctx2.set_option(vb.VL_OPT_XCD_ORDER, 1 - xcd)
-        ctx2.set_option(vb.VL_OPT_FUSE_SOURCES, 1 - fuse)
+        ctx2.set_option(vb.VL_OPT_FUSE_SOURCES, (fuse + 1) % 3)
         ctx2.set_option(vb.VL_OPT_FUSE_XY, 1 - fxy)
         ctx2.set_option(vb.VL_OPT_X_LANE_LINES, 24 - lpw)  # 16 <-> 8
         ctx2.tune(cache)
