@@ -209,15 +209,15 @@ __device__ __forceinline__ void xl_store(const float (&o)[K], __amdgpu_buffer_rs
 
 constexpr int kXlAhead = 2;
 
-template <int K>
+template <int K, bool CARRY>
 __global__ void __launch_bounds__(256)
 sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *__restrict__ xl32,
          float *__restrict__ field, float *__restrict__ raw, CarriedSources carry)
 {
     // per wave: which of a lane's voxels receive a carried source, and the
     // composites by voxel of the line
-    __shared__ unsigned cs_mask[4][64];
-    __shared__ float2 cs_ab[4][64 * K];
+    __shared__ unsigned cs_mask[4][CARRY ? 64 : 1];
+    __shared__ float2 cs_ab[4][CARRY ? 64 * K : 1];
     constexpr int KM = K > 1 ? K - 1 : 1;
     const int parts = (kTileLines / 4) / lpw;  // workgroups per tile
     const int blk = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -297,47 +297,67 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     auto from_lane = [](int addr, float x) {
         return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
     };
-    // cell sources of the previous step carried into this solve (uniform)
-    const SimCells *CC = carry.enabled ? &carry.cells[S.sim] : nullptr;
+    // cell sources of the previous step carried into this solve (uniform):
+    // each x-line's range [e0, e1) of the voxel-ordered occupied voxels, the
+    // voxels, and their FP32 composites (A, 1/B) of this substrate
+    const SimCells *CC = CARRY ? &carry.cells[S.sim] : nullptr;
     const bool carried = CC != nullptr && CC->xs_base >= 0;
-    const int *__restrict__ xs = carried ? carry.xline_start + CC->xs_base : nullptr;
-    const int *__restrict__ ov = carried ? carry.occ_vox_v + CC->occ_base : nullptr;
-    const float2 *__restrict__ cab = carried ? carry.comp_v + CC->comp_base + S.sub : nullptr;
+    const int c_occ = carried ? CC->n_occ : 0;
     const int cns = carried ? CC->ns : 0;
-    // rho <- (rho + A) * (1/B) on the occupied voxels of line `row`, entries
-    // [e0, e1) of the voxel-ordered list, 64 at a time: each entry's lane
-    // writes its composite to the wave's LDS slot of that voxel and marks the
-    // voxel in its owner lane's mask; owners then update their registers.
-    auto carry_in = [&](const int row, float (&r)[K]) {
-        const int e0 = xs[row], e1 = xs[row + 1];
-        for (int c0 = e0; c0 < e1; c0 += 64) {  // uniform
-            const int e = c0 + lane;
-            const bool ok = e < e1;
-            int i = 0;
-            float2 ab = make_float2(0.f, 1.f);
-            if (ok) {
-                i = ov[e] - row * nx;
-                ab = cab[(size_t)e * cns];
-            }
-            // Lanes talk through LDS here: the wavefront-scope fences keep
-            // the compiler from moving these accesses across the phases (or
-            // forwarding a lane's own cleared mask to its read); the wave's
-            // LDS operations themselves execute in order.
-            cs_mask[wave][lane] = 0u;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            if (ok) {
-                atomicOr(&cs_mask[wave][i / K], 1u << (i % K));
-                cs_ab[wave][i] = ab;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            const unsigned mk = cs_mask[wave][lane];
+    const __amdgpu_buffer_rsrc_t xs_r =
+        make_rsrc(carried ? (const float *)(carry.xline_start + CC->xs_base) : field, carried ? nrows + 1 : 0);
+    const __amdgpu_buffer_rsrc_t ov_r =
+        make_rsrc(carried ? (const float *)(carry.occ_vox_v + CC->occ_base) : field, c_occ);
+    const __amdgpu_buffer_rsrc_t ab_r =
+        make_rsrc(carried ? (const float *)(carry.comp_v + CC->comp_base) : field, 2LL * c_occ * cns);
+    // a line's range (0, 0 for a line not to be touched)
+    auto load_range = [&](int row, bool want) -> vl_u32x2 {
+        return __builtin_amdgcn_raw_buffer_load_b64(xs_r, (int)(want ? (unsigned)row * 4u : kOff), 0, 0);
+    };
+    // this lane's entry of the chunk starting at c0 (voxel, composite)
+    auto load_entry = [&](int c0, int e1, int &vox, float2 &ab) {
+        const int e = c0 + lane;
+        const bool ok = e < e1;
+        vox = (int)__builtin_amdgcn_raw_buffer_load_b32(ov_r, (int)(ok ? (unsigned)e * 4u : kOff), 0, 0);
+        const vl_u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(
+            ab_r, (int)(ok ? ((unsigned)e * (unsigned)cns + (unsigned)S.sub) * 8u : kOff), 0, 0);
+        ab = make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
+    };
+    // rho <- (rho + A) * (1/B) on the occupied voxels of the chunk: each
+    // entry's lane writes its composite to the wave's LDS slot of that voxel
+    // and marks the voxel in its owner lane's mask; owners then update their
+    // registers.  Lanes talk through LDS here: the wavefront-scope fences keep
+    // the compiler from moving these accesses across the phases (or
+    // forwarding a lane's own cleared mask to its read); the wave's LDS
+    // operations themselves execute in order.
+    auto apply_chunk = [&](bool ok, int i, float2 ab, float (&r)[K]) {
+        cs_mask[wave][lane] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (ok) {
+            atomicOr(&cs_mask[wave][i / K], 1u << (i % K));
+            cs_ab[wave][i] = ab;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const unsigned mk = cs_mask[wave][lane];
 #pragma unroll
-            for (int t = 0; t < K; ++t)
-                if (mk & (1u << t)) {
-                    const float2 q = cs_ab[wave][K * lane + t];
-                    r[t] = (r[t] + q.x) * q.y;
-                }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int t = 0; t < K; ++t)
+            if (mk & (1u << t)) {
+                const float2 q = cs_ab[wave][K * lane + t];
+                r[t] = (r[t] + q.x) * q.y;
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    // the line's carried sources: the first 64 entries were loaded ahead with
+    // the line, any further ones are loaded here
+    auto carry_in = [&](const int row, float (&r)[K], vl_u32x2 rg, int vox0, float2 ab0) {
+        const int e0 = __builtin_amdgcn_readfirstlane((int)rg.x), e1 = __builtin_amdgcn_readfirstlane((int)rg.y);
+        if (e1 <= e0) return;  // uniform
+        apply_chunk(e0 + lane < e1, vox0 - row * nx, ab0, r);
+        for (int c0 = e0 + 64; c0 < e1; c0 += 64) {  // uniform
+            int vox;
+            float2 ab;
+            load_entry(c0, e1, vox, ab);
+            apply_chunk(c0 + lane < e1, vox - row * nx, ab, r);
         }
     };
 
@@ -347,10 +367,11 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
 
     // One line.  With FULL (n a multiple of K) every active lane holds K
     // voxels, so the per-lane interval length is the constant K - 1.
-    auto solve_line = [&](auto full_c, auto carry_c, const int row, const int j, const int k, float (&r)[K]) {
+    auto solve_line = [&](auto full_c, auto carry_c, const int row, const int j, const int k, float (&r)[K],
+                          vl_u32x2 rg, int vox0, float2 ab0) {
         constexpr bool FULL = decltype(full_c)::value;
         const int mm = FULL ? K - 1 : m;
-        if (decltype(carry_c)::value) carry_in(row, r);
+        if (decltype(carry_c)::value) carry_in(row, r, rg, vox0, ab0);
         // Dirichlet projection before the solve: the end voxels of the line
         r[0] = set_in_lo ? v_in_lo : r[0];
 #pragma unroll
@@ -435,22 +456,47 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     // fixed registers: before line l is solved, the load of line
     // l + kXlAhead goes into the slot that line l - 1 used (free by then), so
     // kXlAhead loads stay in flight behind every solve.  Lanes with no voxels
-    // load from past the buffer and read zeros.
+    // load from past the buffer and read zeros.  With carried sources a slot
+    // also holds its line's entry range (loaded with the line) and this
+    // lane's first entry (loaded one line later, once the range is in).
     auto run = [&](auto full_c, auto carry_c) {
+        constexpr bool CL = decltype(carry_c)::value;
         constexpr int NS = kXlAhead + 1;
         const int kLines = lpw;
         int j = row0 % ny, k = row0 / ny;  // the line being solved
         float rn[NS][K];
+        vl_u32x2 rg[NS];
+        int ev[NS];
+        float2 eab[NS];
 #pragma unroll
-        for (int a = 0; a < kXlAhead; ++a) xl_load<K>(rn[a], rs, line_off(row0 + a, a < kLines && row0 + a < nrows));
+        for (int a = 0; a < NS; ++a) {
+            rg[a] = vl_u32x2{0u, 0u};
+            ev[a] = 0;
+            eab[a] = make_float2(0.f, 1.f);
+        }
+#pragma unroll
+        for (int a = 0; a < kXlAhead; ++a) {
+            const bool want = a < kLines && row0 + a < nrows;
+            xl_load<K>(rn[a], rs, line_off(row0 + a, want));
+            if (CL) rg[a] = load_range(row0 + a, want);
+        }
+        if (CL)
+#pragma unroll
+            for (int a = 0; a + 1 < kXlAhead; ++a) load_entry((int)rg[a].x, (int)rg[a].y, ev[a], eab[a]);
         for (int g = 0; g < kLines; g += NS) {
 #pragma unroll
             for (int a = 0; a < NS; ++a) {
                 const int row = row0 + g + a;
                 const int nrow = row + kXlAhead;
-                xl_load<K>(rn[(a + kXlAhead) % NS], rs, line_off(nrow, g + a + kXlAhead < kLines && nrow < nrows));
+                const bool want = g + a + kXlAhead < kLines && nrow < nrows;
+                xl_load<K>(rn[(a + kXlAhead) % NS], rs, line_off(nrow, want));
+                if (CL) {
+                    rg[(a + kXlAhead) % NS] = load_range(nrow, want);
+                    const int sm = (a + kXlAhead - 1) % NS;  // the line after this one
+                    load_entry((int)rg[sm].x, (int)rg[sm].y, ev[sm], eab[sm]);
+                }
                 if (g + a < kLines && row < nrows) {  // wave-uniform
-                    solve_line(full_c, carry_c, row, j, k, rn[a]);
+                    solve_line(full_c, carry_c, row, j, k, rn[a], rg[a], ev[a], eab[a]);
                     if (++j == ny) {
                         j = 0;
                         ++k;
@@ -459,13 +505,15 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
             }
         }
     };
-    if (carried) {
-        if (n % K == 0) run(std::true_type{}, std::true_type{});
-        else run(std::false_type{}, std::true_type{});
-    } else {
-        if (n % K == 0) run(std::true_type{}, std::false_type{});
-        else run(std::false_type{}, std::false_type{});
+    if constexpr (CARRY) {
+        if (carried) {
+            if (n % K == 0) run(std::true_type{}, std::true_type{});
+            else run(std::false_type{}, std::true_type{});
+            return;
+        }
     }
+    if (n % K == 0) run(std::true_type{}, std::false_type{});
+    else run(std::false_type{}, std::false_type{});
 }
 
 hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32,
@@ -478,7 +526,12 @@ hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *s
     const dim3 grid((unsigned)blocks), block(256);
     switch (K) {
 #define VL_XL_CASE(k)                                                                                  \
-    case k: hipLaunchKernelGGL((sweep_xl<k>), grid, block, 0, st, L, lpw, subs, xl32, field, raw, carry); break;
+    case k:                                                                                            \
+        if (carry.enabled)                                                                             \
+            hipLaunchKernelGGL((sweep_xl<k, true>), grid, block, 0, st, L, lpw, subs, xl32, field, raw, carry); \
+        else                                                                                           \
+            hipLaunchKernelGGL((sweep_xl<k, false>), grid, block, 0, st, L, lpw, subs, xl32, field, raw, carry); \
+        break;
         VL_XL_CASE(1)
         VL_XL_CASE(2)
         VL_XL_CASE(4)
