@@ -47,11 +47,11 @@ def source_digest(files) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, launch: dict | None = None):
     """HBM bytes per launch of a kernel from the committed FETCH_SIZE /
     WRITE_SIZE measurements (scaled by the copy-kernel calibration), or None
-    when there is none for this workload or the kernel's sources changed
-    since the counters were taken."""
+    when there is none for this workload and launch configuration, or the
+    kernel's sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             table = json.load(f)
@@ -59,6 +59,8 @@ def measured_traffic(workload: str, kernel: str):
         return None
     for e in table.get("entries", []):
         if e.get("workload") == workload and e.get("kernel") == kernel:
+            if launch is not None and e.get("launch") != launch:
+                continue
             if e.get("sources_sha256") != source_digest(e.get("sources", [])):
                 return None
             return int(e["bytes_read"] + e["bytes_written"])
@@ -310,6 +312,9 @@ def main():
     xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))
     x_lanes = bool(ctx.get_option(vb.VL_OPT_X_LANES)) if precision == vb.VL_F32 else False
     x_lane_lines = ctx.get_option(vb.VL_OPT_X_LANE_LINES) if x_lanes else None
+    # what the per-kernel traffic measurements are keyed by, besides the workload
+    launch_cfg = {"cell_sources": fuse_src, "x_lanes_along_line": x_lanes, "x_lines_per_wave": x_lane_lines,
+                  "xcd_order": xcd_ord}
     for k, s in enumerate(wl.sims):
         ctx.set_field(k, s.rho0)
     elapsed = time_steps(ctx, args.steps, args.warmup)
@@ -346,7 +351,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(alg_bytes / (per_step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if alg_bytes else None,
-        "traffic": measured_traffic(wl.name, dom),
+        "traffic": measured_traffic(wl.name, dom, launch_cfg),
         "avg_ms": round(per_step_ms / launches_per_step, 5),
         "launches_per_step": launches_per_step,
         "bytes_per_launch": alg_bytes / launches_per_step if alg_bytes else None,

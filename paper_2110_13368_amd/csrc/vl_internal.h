@@ -96,6 +96,8 @@ struct SimCells {
     int xs_base;     // first entry of the x-line starts (ny*nz + 1) when this simulation's sources
                      // can be carried into the next x solve (FP32, x-lines solved with the lanes
                      // along the line, cells present), else -1
+    int occ_cap;     // occupied voxels the tables have room for (the voxel-ordered composites
+                     // are substrate-major with this stride)
 };
 
 // Cell sources applied by the z sweep after its stores (FP32 path).  The
@@ -113,7 +115,7 @@ struct FusedSources {
 // Cell sources of the previous step applied by the x solve (lanes along the
 // line) to each line as it is loaded, before the Dirichlet projection: the
 // occupied voxels in voxel order, each x-line's first entry (xs_base), their
-// FP32 composites in the same order.
+// FP32 composites in the same order, substrate-major (stride occ_cap).
 struct CarriedSources {
     const SimCells *cells;
     const int *xline_start;
@@ -212,8 +214,8 @@ hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start,
                              int n_occ, int ns, const double *V, const double *S,
                              const double *U, const double *RS, double dt, double vvox,
-                             const int *pos, float2 *comp32, float2 *comp32_v, double2 *ab64,
-                             double *krs, double *kcell, int *cell_of, hipStream_t st);
+                             const int *pos, float2 *comp32, float2 *comp32_v, int v_stride,
+                             double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st);
 hipError_t launch_xline_starts(const int *occ_vox_v, int n_occ, int nx, int nlines, int *line_start,
                                hipStream_t st);
 hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,

@@ -446,7 +446,7 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
                                   const double *__restrict__ V, const double *__restrict__ S,
                                   const double *__restrict__ U, const double *__restrict__ RS,
                                   double dt, double vvox, const int *__restrict__ pos,
-                                  float2 *__restrict__ comp32, float2 *__restrict__ comp32_v,
+                                  float2 *__restrict__ comp32, float2 *__restrict__ comp32_v, int v_stride,
                                   double2 *__restrict__ ab64, double *__restrict__ krs,
                                   double *__restrict__ kcell, int *__restrict__ cell_of)
 {
@@ -470,19 +470,19 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
     }
     const float2 c32 = make_float2((float)A, (float)(1.0 / B));
     if (comp32) comp32[(size_t)out * ns + s] = c32;
-    if (comp32_v) comp32_v[(size_t)seg * ns + s] = c32;
+    if (comp32_v) comp32_v[(size_t)s * v_stride + seg] = c32;  // substrate-major
 }
 
 hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, int n_occ, int ns,
                              const double *V, const double *S, const double *U, const double *RS,
                              double dt, double vvox, const int *pos, float2 *comp32, float2 *comp32_v,
-                             double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st)
+                             int v_stride, double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st)
 {
     const long long total = (long long)n_occ * ns;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(composites_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys,
-                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, comp32_v, ab64, krs, kcell,
-                       cell_of);
+                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, comp32_v, v_stride, ab64, krs,
+                       kcell, cell_of);
     return hipGetLastError();
 }
 

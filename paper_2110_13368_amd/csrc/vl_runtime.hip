@@ -426,7 +426,7 @@ int upload_cell_tables(vl_ctx *ctx)
         const SimHost &s = ctx->sims[k];
         cells[k] = vl::SimCells{s.sub0,       s.ns,      s.n_occ,   s.occ_base,
                                 s.occ_base,   s.comp_base, s.ab_base, s.zl_base,
-                                s.n_occ > 0 ? s.xs_base : -1};
+                                s.n_occ > 0 ? s.xs_base : -1, s.max_cells};
         prefix[k + 1] = prefix[k] + s.n_occ;
     }
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_cells, cells.data(), cells.size() * sizeof(vl::SimCells),
@@ -1160,7 +1160,7 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
                                      ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S),
                                      ctx->at<double>(ctx->o_U), ctx->at<double>(ctx->o_RS), ctx->dt, vvox,
                                      pos, zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
-                                     zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr,
+                                     zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr, s.max_cells,
                                      ctx->at<double2>(ctx->o_ab) + s.ab_base,
                                      zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
                                      zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,

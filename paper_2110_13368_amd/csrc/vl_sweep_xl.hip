@@ -299,17 +299,18 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     };
     // cell sources of the previous step carried into this solve (uniform):
     // each x-line's range [e0, e1) of the voxel-ordered occupied voxels, the
-    // voxels, and their FP32 composites (A, 1/B) of this substrate
+    // voxels, and their FP32 composites (A, 1/B) of this substrate (one
+    // contiguous run per substrate)
     const SimCells *CC = CARRY ? &carry.cells[S.sim] : nullptr;
     const bool carried = CC != nullptr && CC->xs_base >= 0;
     const int c_occ = carried ? CC->n_occ : 0;
-    const int cns = carried ? CC->ns : 0;
     const __amdgpu_buffer_rsrc_t xs_r =
         make_rsrc(carried ? (const float *)(carry.xline_start + CC->xs_base) : field, carried ? nrows + 1 : 0);
     const __amdgpu_buffer_rsrc_t ov_r =
         make_rsrc(carried ? (const float *)(carry.occ_vox_v + CC->occ_base) : field, c_occ);
     const __amdgpu_buffer_rsrc_t ab_r =
-        make_rsrc(carried ? (const float *)(carry.comp_v + CC->comp_base) : field, 2LL * c_occ * cns);
+        make_rsrc(carried ? (const float *)(carry.comp_v + CC->comp_base + (size_t)S.sub * CC->occ_cap) : field,
+                  2LL * c_occ);
     // a line's range (0, 0 for a line not to be touched)
     auto load_range = [&](int row, bool want) -> vl_u32x2 {
         return __builtin_amdgcn_raw_buffer_load_b64(xs_r, (int)(want ? (unsigned)row * 4u : kOff), 0, 0);
@@ -319,8 +320,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
         const int e = c0 + lane;
         const bool ok = e < e1;
         vox = (int)__builtin_amdgcn_raw_buffer_load_b32(ov_r, (int)(ok ? (unsigned)e * 4u : kOff), 0, 0);
-        const vl_u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(
-            ab_r, (int)(ok ? ((unsigned)e * (unsigned)cns + (unsigned)S.sub) * 8u : kOff), 0, 0);
+        const vl_u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(ab_r, (int)(ok ? (unsigned)e * 8u : kOff), 0, 0);
         ab = make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
     };
     // rho <- (rho + A) * (1/B) on the occupied voxels of the chunk: each
