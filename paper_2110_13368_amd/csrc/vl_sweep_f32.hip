@@ -151,9 +151,17 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
             }
         }
     } else {
+        // Every row of the capacity is loaded, the rows past this wave's
+        // half from an offset beyond the buffer (they read 0 and touch no
+        // memory): with no branch around the loads the waits before the
+        // elimination can be for the first rows only.
         const int row0 = top ? 0 : (n - 1) * row_b;
         const int step = top ? row_b : -row_b;
-        VL_FOR_UP(CAP, nel, t, v[t] = bload(rs, lane_b, row0 + t * step);)
+#pragma unroll
+        for (int t = 0; t < CAP; ++t) {
+            const unsigned oob = (unsigned)((nel - 1 - t) >> 31) & 0x80000000u;  // uniform
+            v[t] = bload(rs, lane_b | oob, oob ? 0 : row0 + t * step);
+        }
     }
 
     __syncthreads();  // pivot table visible
