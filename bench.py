@@ -188,6 +188,10 @@ def run_adjoint(args):
     print(f"bench: adjoint of {wl.name}: {E} voxel-substrates, {n_steps} steps, checkpoint every {ckpt}",
           file=sys.stderr, flush=True)
     ctx = vb.Context(wl.sims)
+    ctx.tune(None)  # launch configuration of the forward steps and replays; setup, not timed
+    for k, s in enumerate(wl.sims):
+        ctx.set_field(k, s.rho0)
+    x_lanes_opt = ctx.get_option(vb.VL_OPT_X_LANES)
     rng = np.random.default_rng(211013368 + 40)
     grads = [rng.normal(size=s.field_shape) for s in wl.sims]
     g = ctx.to_field_layout([a.astype(np.float32) for a in grads])
@@ -247,7 +251,7 @@ def run_adjoint(args):
         "data": "synthetic (seeded generators shaped like the paper's tumour workloads)",
         "config": {"workload": wl.name, "voxel_substrates": E, "grid": list(wl.sims[0].shape),
                    "n_sub": wl.sims[0].n_sub, "cells": int(wl.sims[0].cells.n), "ckpt_every": ckpt,
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu", "x_lanes_min_line": {0: None, 1: 129, 2: 65}[x_lanes_opt]},
         "gradients": {"dD": [float(x) for x in dD], "dlambda": [float(x) for x in dl]},
         "roofline": roofline, "kernels": kernels,
     }
@@ -268,8 +272,9 @@ def main():
     ap.add_argument("--no-copy-reference", action="store_true")
     ap.add_argument("--mode", default="tuned", choices=["tuned", "launches", "persistent"])
     ap.add_argument("--ckpt-every", type=int, default=20)
-    ap.add_argument("--x-lanes", default="auto", choices=["auto", "0", "1"],
-                    help="force the x solve (after tuning): 1 lanes along the line, 0 split solve")
+    ap.add_argument("--x-lanes", default="auto", choices=["auto", "0", "1", "2"],
+                    help="force the x solve (after tuning): lanes along lines of 129+ (1) or 65+ (2) voxels, "
+                         "0 split solve")
     ap.add_argument("--x-lane-lines", default="auto", choices=["auto", "1", "2", "4", "8", "16"],
                     help="force the x-lines per wave of the lanes-along-the-line solve (after tuning)")
     ap.add_argument("--sources", default="auto", choices=["auto", "0", "1", "2"],
@@ -310,7 +315,8 @@ def main():
     fuse_src = {0: "own kernel", 1: "in the z sweep", 2: "carried into the next x solve"}[
         ctx.get_option(vb.VL_OPT_FUSE_SOURCES)] if precision == vb.VL_F32 else "own kernel"
     xcd_ord = bool(ctx.get_option(vb.VL_OPT_XCD_ORDER))
-    x_lanes = bool(ctx.get_option(vb.VL_OPT_X_LANES)) if precision == vb.VL_F32 else False
+    x_lanes_opt = ctx.get_option(vb.VL_OPT_X_LANES) if precision == vb.VL_F32 else 0
+    x_lanes = bool(x_lanes_opt)
     x_lane_lines = ctx.get_option(vb.VL_OPT_X_LANE_LINES) if x_lanes else None
     # what the per-kernel traffic measurements are keyed by, besides the workload
     launch_cfg = {"cell_sources": fuse_src, "x_lanes_along_line": x_lanes, "x_lines_per_wave": x_lane_lines,
@@ -390,7 +396,8 @@ def main():
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
                    "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode,
                    "xy_per_plane": fused_xy, "cell_sources": fuse_src, "xcd_order": xcd_ord,
-                   "x_lanes_along_line": x_lanes, "x_lines_per_wave": x_lane_lines},
+                   "x_lanes_along_line": x_lanes, "x_lanes_min_line": {0: None, 1: 129, 2: 65}[x_lanes_opt],
+                   "x_lines_per_wave": x_lane_lines},
         "hbm_effective": {"basis": "B_alg: three sweeps x (read + write) per voxel-substrate-step; with x and y "
                                    "solved per z-plane the step moves less than B_alg",
                           "bytes_per_update": b_alg,

@@ -228,8 +228,10 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * parallel cyclic reduction with multipliers computed in FP64 when the
  * coefficients are (vl_bind, vl_update_substrates).  The same linear system
  * as the split solve, to rounding.  Shorter lines keep the split solve.
- * Used when x and y are not solved per plane; the adjoint's replay follows
- * it.  0 uses the split solve for every line; vl_tune times both. */
+ * 2 does the same for lines of 65 or more voxels (2 per lane below 129),
+ * which pays on large grids with such lines and not on batches of small
+ * ones.  Used when x and y are not solved per plane; the adjoint's replay
+ * follows it.  0 uses the split solve for every line; vl_tune times them. */
 #define VL_OPT_X_LANES 7
 /* VL_OPT_X_LANE_LINES (FP32 path, default 8): x-lines each wave of that
  * solve takes one after another: 1, 2, 4, 8 or 16.  A workgroup is four

@@ -68,7 +68,8 @@ struct SubDev {
 //                              is not empty, else 0
 constexpr int kXLaneMaxK = 9;  // lines of up to 576 voxels
 constexpr int kXLaneLevels = 6;
-constexpr int kXLaneMinN = 129;  // shorter lines keep the split solve (few voxels per lane)
+constexpr int kXLaneMinN = 129;       // shorter lines keep the split solve (few voxels per lane)
+constexpr int kXLaneMinNShort = 65;   // the same with two voxels per lane (VL_OPT_X_LANES 2)
 __host__ __device__ constexpr int xl_fields(int K) { return 4 * (K - 1) + 2 * kXLaneLevels + 3; }
 // voxels per lane: whole 16-byte pieces where the line allows
 __host__ __device__ constexpr int xl_k(int n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 9; }

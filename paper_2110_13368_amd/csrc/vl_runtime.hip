@@ -116,10 +116,12 @@ struct vl_ctx {
     std::vector<Launch> xy_launches;
     // x solve with lanes along the line: launches grouped by voxels per lane
     // (cap_idx holds K) and the per-volume tables
-    bool x_lanes = true;
+    int x_lanes = 1;  // 0 split x solve everywhere; 1 lanes along lines of 129+ voxels; 2 of 65+
     int xl_lpw = kDefaultXLaneLines;  // x-lines per wave of the lanes-along-the-line solve
-    std::vector<Launch> xl_launches;       // long lines: lanes along the line
-    std::vector<Launch> xl_rest_launches;  // the other volumes' split x sweeps
+    // per x_lanes setting (index x_lanes - 1): the volumes solved with lanes
+    // along the line, and the other volumes' split x sweeps
+    std::vector<Launch> xl_launches[2];
+    std::vector<Launch> xl_rest_launches[2];
     size_t n_xl32 = 0;
     size_t xy_lds_max = 0;
     bool xcd_order = true;
@@ -325,9 +327,9 @@ int enqueue_step(vl_ctx *ctx, int phase)
         };
         for (int axis = 0; axis < 3; ++axis) {
             if (!xy && axis == 0 && ctx->x_lanes) {
-                for (const Launch &L : ctx->xl_rest_launches)
+                for (const Launch &L : ctx->xl_rest_launches[ctx->x_lanes - 1])
                     if ((rc = sweep(L))) return rc;
-                for (const Launch &L : ctx->xl_launches) {
+                for (const Launch &L : ctx->xl_launches[ctx->x_lanes - 1]) {
                     vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
                                       ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
                                       ctx->xcd_order ? 1 : 0};
@@ -730,53 +732,56 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     // x with lanes along the line: volumes with lines of at least
     // kXLaneMinN voxels grouped by voxels per lane; the split x sweeps of the
     // others
-    ctx->xl_launches.clear();
-    ctx->xl_rest_launches.clear();
-    if (ctx->precision == VL_F32) {
-        auto long_x = [&](int q) { return ctx->subs[q].xlane >= 0 && ctx->subs[q].n[0] >= vl::kXLaneMinN; };
-        std::vector<std::vector<int>> groups(vl::kNumCaps);
-        for (int q = 0; q < nsubs; ++q)
-            if (!long_x(q)) groups[cap_index(ctx->subs[q].n[0] - 1 - (ctx->subs[q].n[0] - 1) / 2)].push_back(q);
-        for (int ci = 0; ci < vl::kNumCaps; ++ci) {
-            if (groups[ci].empty()) continue;
-            Launch L;
-            L.axis = 0;
-            L.cap_idx = ci;
-            L.count = (int)groups[ci].size();
-            L.ids_off = ctx->itable.size();
-            for (int q : groups[ci]) ctx->itable.push_back(q);
-            L.prefix_off = ctx->itable.size();
-            long long acc = 0;
-            for (int q : groups[ci]) {
-                ctx->itable.push_back((int)acc);
-                const SubDev &d = ctx->subs[q];
-                acc += (d.vol / d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
-            }
-            ctx->itable.push_back((int)acc);
-            L.total_tiles = (int)acc;
-            ctx->xl_rest_launches.push_back(L);
-        }
-        for (int K = 1; K <= vl::kXLaneMaxK; ++K) {
-            std::vector<int> ids;
+    for (int setting = 0; setting < 2; ++setting) {
+        ctx->xl_launches[setting].clear();
+        ctx->xl_rest_launches[setting].clear();
+        const int min_n = setting == 0 ? vl::kXLaneMinN : vl::kXLaneMinNShort;
+        if (ctx->precision == VL_F32) {
+            auto long_x = [&](int q) { return ctx->subs[q].xlane >= 0 && ctx->subs[q].n[0] >= min_n; };
+            std::vector<std::vector<int>> groups(vl::kNumCaps);
             for (int q = 0; q < nsubs; ++q)
-                if (long_x(q) && vl::xl_k(ctx->subs[q].n[0]) == K) ids.push_back(q);
-            if (ids.empty()) continue;
-            Launch L;
-            L.axis = 0;
-            L.cap_idx = K;
-            L.count = (int)ids.size();
-            L.ids_off = ctx->itable.size();
-            for (int q : ids) ctx->itable.push_back(q);
-            L.prefix_off = ctx->itable.size();
-            long long acc = 0;
-            for (int q : ids) {
+                if (!long_x(q)) groups[cap_index(ctx->subs[q].n[0] - 1 - (ctx->subs[q].n[0] - 1) / 2)].push_back(q);
+            for (int ci = 0; ci < vl::kNumCaps; ++ci) {
+                if (groups[ci].empty()) continue;
+                Launch L;
+                L.axis = 0;
+                L.cap_idx = ci;
+                L.count = (int)groups[ci].size();
+                L.ids_off = ctx->itable.size();
+                for (int q : groups[ci]) ctx->itable.push_back(q);
+                L.prefix_off = ctx->itable.size();
+                long long acc = 0;
+                for (int q : groups[ci]) {
+                    ctx->itable.push_back((int)acc);
+                    const SubDev &d = ctx->subs[q];
+                    acc += (d.vol / d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
+                }
                 ctx->itable.push_back((int)acc);
-                const SubDev &d = ctx->subs[q];
-                acc += (d.vol / d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
+                L.total_tiles = (int)acc;
+                ctx->xl_rest_launches[setting].push_back(L);
             }
-            ctx->itable.push_back((int)acc);
-            L.total_tiles = (int)acc;
-            ctx->xl_launches.push_back(L);
+            for (int K = 1; K <= vl::kXLaneMaxK; ++K) {
+                std::vector<int> ids;
+                for (int q = 0; q < nsubs; ++q)
+                    if (long_x(q) && vl::xl_k(ctx->subs[q].n[0]) == K) ids.push_back(q);
+                if (ids.empty()) continue;
+                Launch L;
+                L.axis = 0;
+                L.cap_idx = K;
+                L.count = (int)ids.size();
+                L.ids_off = ctx->itable.size();
+                for (int q : ids) ctx->itable.push_back(q);
+                L.prefix_off = ctx->itable.size();
+                long long acc = 0;
+                for (int q : ids) {
+                    ctx->itable.push_back((int)acc);
+                    const SubDev &d = ctx->subs[q];
+                    acc += (d.vol / d.n[0] + vl::kTileLines - 1) / vl::kTileLines;
+                }
+                ctx->itable.push_back((int)acc);
+                L.total_tiles = (int)acc;
+                ctx->xl_launches[setting].push_back(L);
+            }
         }
     }
     // one-launch step: every volume, tiles of x, then y, then z in one queue
@@ -1301,9 +1306,9 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         return VL_OK;
     }
     if (option == VL_OPT_X_LANES) {
-        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_X_LANES takes 0 or 1");
-        if (ctx->x_lanes != (value == 1)) drop_graph(ctx);
-        ctx->x_lanes = value == 1;
+        if (value < 0 || value > 2) return fail(VL_E_ARG, "VL_OPT_X_LANES takes 0, 1 or 2");
+        if (ctx->x_lanes != value) drop_graph(ctx);
+        ctx->x_lanes = value;
         return VL_OK;
     }
     if (option == VL_OPT_X_LANE_LINES) {
@@ -1345,7 +1350,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     case VL_OPT_WAIT_LIMIT_US: *value = ctx->wait_limit_us; return VL_OK;
     case VL_OPT_XCD_ORDER: *value = ctx->xcd_order ? 1 : 0; return VL_OK;
     case VL_OPT_FUSE_XY: *value = ctx->fuse_xy ? 1 : 0; return VL_OK;
-    case VL_OPT_X_LANES: *value = ctx->x_lanes ? 1 : 0; return VL_OK;
+    case VL_OPT_X_LANES: *value = ctx->x_lanes; return VL_OK;
     case VL_OPT_X_LANE_LINES: *value = ctx->xl_lpw; return VL_OK;
     default: return fail(VL_E_ARG, "unknown option");
     }
@@ -1415,13 +1420,17 @@ int vl_tune(vl_ctx *ctx, const char *cache_path)
     std::vector<Cand> cands;
     const bool any_plane = ctx->xy_ready;
     for (int xy = 0; xy <= (any_plane ? 1 : 0); ++xy)
-        for (int xl = xy ? 0 : 1; xl >= 0; --xl)
-            for (int xcd = 1; xcd >= 0; --xcd)
+        for (int xl : {1, 2, 0}) {
+            if (xy && xl) continue;
+            for (int xcd = 1; xcd >= 0; --xcd) {
+                if (xl == 2 && !xcd) continue;
                 for (int fuse : {1, 2, 0}) {
                     if (fuse == 2 && !xl) continue;
                     cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, kDefaultXLaneLines});
-                    if (xl && xcd) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, 16});
+                    if (xl == 1 && xcd) cands.push_back({VL_MODE_LAUNCHES, 0, xcd, fuse, xy, xl, 16});
                 }
+            }
+        }
     if (one_launch_enabled()) {
         int per_cu = 1, cus = 1, dev = 0;
         VL_HIP(hipGetDevice(&dev));
@@ -1572,8 +1581,8 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
     // split sweeps otherwise; then y and z
     std::vector<std::pair<const Launch *, bool>> order;  // (launch, lanes along the line)
     if (ctx->x_lanes) {
-        for (const Launch &L : ctx->xl_rest_launches) order.push_back({&L, false});
-        for (const Launch &L : ctx->xl_launches) order.push_back({&L, true});
+        for (const Launch &L : ctx->xl_rest_launches[ctx->x_lanes - 1]) order.push_back({&L, false});
+        for (const Launch &L : ctx->xl_launches[ctx->x_lanes - 1]) order.push_back({&L, true});
     } else {
         for (const Launch &L : ctx->launches)
             if (L.axis == 0) order.push_back({&L, false});

@@ -115,6 +115,9 @@ def test_options_on_the_host():
         vb.vl_set_option(h, vb.VL_OPT_X_LANES, 0)
         assert vb.vl_get_option(h, vb.VL_OPT_X_LANES) == 0
         assert _code(vb.vl_set_option, h, vb.VL_OPT_X_LANES, -1) == vb.VL_E_ARG
+        vb.vl_set_option(h, vb.VL_OPT_X_LANES, 2)  # lines of 65 voxels and more
+        assert vb.vl_get_option(h, vb.VL_OPT_X_LANES) == 2
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_X_LANES, 3) == vb.VL_E_ARG
         assert vb.vl_get_option(h, vb.VL_OPT_X_LANE_LINES) in (1, 2, 4, 8, 16)
         for v in (1, 2, 4, 8, 16):
             vb.vl_set_option(h, vb.VL_OPT_X_LANE_LINES, v)

@@ -89,12 +89,13 @@ def test_adjoint_matches_oracle(mode, shape, bc):
 
 
 @pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
-def test_adjoint_with_x_lanes_forward(mode):
+@pytest.mark.parametrize("shape,x_lanes", [((130, 13, 9), 1), ((100, 11, 7), 2), ((70, 6, 5), 2)])
+def test_adjoint_with_x_lanes_forward(mode, shape, x_lanes):
     # forward steps and replays use the lanes-along-the-line x solve
-    spec, target = _case(123, (130, 13, 9), bc="mixed", n_cells=30)
+    spec, target = _case(123, shape, bc="mixed", n_cells=30)
     o, r = _oracle_grads(spec, target, mode, 6)
-    g = _gpu_grads([spec], [r], mode, 6, ckpt=4, x_lanes=1)[0]
-    _compare(g, o, f"x lanes mode {mode}")
+    g = _gpu_grads([spec], [r], mode, 6, ckpt=4, x_lanes=x_lanes)[0]
+    _compare(g, o, f"x lanes {x_lanes} {shape} mode {mode}")
 
 
 @pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])

@@ -61,11 +61,12 @@ def _batch():
 
 
 @pytest.mark.parametrize("steps", [1, 2, 5])
-def test_carried_sources_equal_other_modes(steps):
+@pytest.mark.parametrize("x_lanes", [1, 2])
+def test_carried_sources_equal_other_modes(steps, x_lanes):
     specs = _batch()
-    f2, n2 = run_gpu(specs, steps, x_lanes=1, sources_mode=2)
-    f1, n1 = run_gpu(specs, steps, x_lanes=1, sources_mode=1)
-    f0, _ = run_gpu(specs, steps, x_lanes=1, sources_mode=0)
+    f2, n2 = run_gpu(specs, steps, x_lanes=x_lanes, sources_mode=2)
+    f1, n1 = run_gpu(specs, steps, x_lanes=x_lanes, sources_mode=1)
+    f0, _ = run_gpu(specs, steps, x_lanes=x_lanes, sources_mode=0)
     assert n1 == n2
     for k in range(len(specs)):
         assert np.array_equal(f2[k], f1[k]), f"sim {k}: carried vs fused into z"

@@ -76,14 +76,16 @@ def test_fp32_line_lengths(n, axis):
 
 @pytest.mark.parametrize("n", X_LANE_LENGTHS)
 @pytest.mark.parametrize("bc", ["mixed", "dirichlet"])
-def test_fp32_x_lanes_line_lengths(n, bc):
+@pytest.mark.parametrize("x_lanes", [1, 2])
+def test_fp32_x_lanes_line_lengths(n, bc, x_lanes):
+    # x_lanes 1: lanes along lines of 129+ voxels, 2: of 65+ voxels
     spec = _spec((n, 5, 3), 2, bc, 12, "f32", n * 7 + len(bc))
-    (got,), _ = run_gpu([spec], 20, x_lanes=1)
+    (got,), _ = run_gpu([spec], 20, x_lanes=x_lanes)
     want = run_oracle(spec, 20)
-    assert_close(got, want, 1e-5, f"x lanes n={n} {bc}")
+    assert_close(got, want, 1e-5, f"x lanes {x_lanes} n={n} {bc}")
 
 
-@pytest.mark.parametrize("x_lanes", [0, 1])
+@pytest.mark.parametrize("x_lanes", [0, 1, 2])
 @pytest.mark.parametrize("decay", DECAYS)
 @pytest.mark.parametrize("bc", ["neumann", "dirichlet", "mixed"])
 def test_fp32_boundary_mixes_and_decay(bc, decay, x_lanes):
@@ -93,7 +95,7 @@ def test_fp32_boundary_mixes_and_decay(bc, decay, x_lanes):
     assert_close(got, want, 1e-5, f"fp32 {bc}")
 
 
-@pytest.mark.parametrize("x_lanes", [0, 1])
+@pytest.mark.parametrize("x_lanes", [0, 1, 2])
 def test_fp32_single_large_scaled_100_steps(x_lanes):
     """The single large simulation at a quarter of its edge (50^3 x 4, Gaussian
     ball of cells), 100 steps."""
@@ -105,7 +107,7 @@ def test_fp32_single_large_scaled_100_steps(x_lanes):
     print("single-large/4 errors per substrate (max, L2):", errs)
 
 
-@pytest.mark.parametrize("x_lanes", [0, 1])
+@pytest.mark.parametrize("x_lanes", [0, 1, 2])
 def test_fp32_batched_ragged(x_lanes):
     wl = W.batched(n_sims=6, edge_range=(7, 70), cells_range=(50, 800))
     fields, n_out = run_gpu(wl.sims, 40, x_lanes=x_lanes)
