@@ -14,6 +14,12 @@
 
 using vl::SubDev;
 
+namespace vl {
+// the adjoint's reverse x solve with the lanes along the line (vl_adjoint_xl.hip)
+hipError_t launch_adjoint_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *w,
+                             const float *raw, double *part, hipStream_t st);
+}  // namespace vl
+
 // x-lines per wave of the lanes-along-the-line solve when not tuned
 constexpr int kDefaultXLaneLines = 8;
 
@@ -1518,10 +1524,29 @@ int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms
 
 struct AdjLayout {
     size_t ck, seg, raw[3], w, part, totals, out_base, bytes;
-    std::vector<size_t> part_off;  // per sweep launch: its tiles' slots in part
+    // per reverse launch: its tiles' slots in part (the split sweeps of every
+    // axis, and per x-lanes setting the split x sweeps of the other volumes
+    // and the lanes-along-the-line x launches); all are laid out whatever
+    // the options, so the workspace size does not depend on them
+    std::vector<size_t> part_off, part_off_rest[2], part_off_xl[2];
     size_t n_slots;
     int nseg, K;
 };
+
+// The reverse sweeps of one step in order (z, y, x) with their partial-sum
+// slots: the split reverse solve for every launch of z and y; for x the split
+// one over every volume, or, with the lanes-along-the-line x solve on, the
+// split one over the other volumes and the lanes one over its volumes (whose
+// replay stored its raw output with that solve).
+struct RevLaunch {
+    const Launch *L;
+    int axis;
+    bool lanes;
+    size_t part_off;
+};
+
+struct AdjLayout;
+static std::vector<RevLaunch> reverse_launches(const vl_ctx *ctx, const AdjLayout &A);
 
 static AdjLayout adj_layout(const vl_ctx *ctx, int n_steps, int K)
 {
@@ -1533,6 +1558,16 @@ static AdjLayout adj_layout(const vl_ctx *ctx, int n_steps, int K)
     for (const Launch &L : ctx->launches) {
         a.part_off.push_back(n_slots);
         n_slots += 3 * (size_t)L.total_tiles;
+    }
+    for (int x = 0; x < 2; ++x) {
+        for (const Launch &L : ctx->xl_rest_launches[x]) {
+            a.part_off_rest[x].push_back(n_slots);
+            n_slots += 3 * (size_t)L.total_tiles;
+        }
+        for (const Launch &L : ctx->xl_launches[x]) {
+            a.part_off_xl[x].push_back(n_slots);
+            n_slots += 3 * (size_t)L.total_tiles;
+        }
     }
     a.n_slots = n_slots;
     size_t w = 0;
@@ -1554,6 +1589,24 @@ static AdjLayout adj_layout(const vl_ctx *ctx, int n_steps, int K)
     w += round_up(sizeof(int) * (ctx->n_sims + 1), 256);
     a.bytes = w;
     return a;
+}
+
+static std::vector<RevLaunch> reverse_launches(const vl_ctx *ctx, const AdjLayout &A)
+{
+    std::vector<RevLaunch> rev;
+    for (int axis = 2; axis >= 0; --axis) {
+        if (axis == 0 && ctx->x_lanes) {
+            const int x = ctx->x_lanes - 1;
+            for (size_t i = 0; i < ctx->xl_rest_launches[x].size(); ++i)
+                rev.push_back({&ctx->xl_rest_launches[x][i], 0, false, A.part_off_rest[x][i]});
+            for (size_t i = 0; i < ctx->xl_launches[x].size(); ++i)
+                rev.push_back({&ctx->xl_launches[x][i], 0, true, A.part_off_xl[x][i]});
+            continue;
+        }
+        for (size_t li = 0; li < ctx->launches.size(); ++li)
+            if (ctx->launches[li].axis == axis) rev.push_back({&ctx->launches[li], axis, false, A.part_off[li]});
+    }
+    return rev;
 }
 
 int vl_adjoint_workspace(vl_ctx *ctx, int n_steps, int ckpt_every, size_t *bytes)
@@ -1661,6 +1714,7 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
     const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
     const float2 *coef = ctx->at<float2>(ctx->o_coef32);
     float *w = (float *)(aws + A.w);
+    const std::vector<RevLaunch> rev = reverse_launches(ctx, A);
     for (int seg = A.nseg - 1; seg >= 0 && n_steps > 0; --seg) {
         const int t0 = seg * K, t1 = std::min(t0 + K, n_steps);
         if (int r = copy(ctx->field, aws + A.ck + F * seg)) return r;
@@ -1681,30 +1735,30 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
                         (const int *)(aws + A.out_base), dS_dev, dU_dev, st);
                 }))
                 return r;
-            for (int axis = 2; axis >= 0; --axis)
-                for (size_t li = 0; li < ctx->launches.size(); ++li) {
-                    const Launch &L = ctx->launches[li];
-                    if (L.axis != axis) continue;
-                    vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off,
-                                      ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles, 0};
-                    if (int r = timed(ctx, VL_K_ADJ_X + axis, [&] {
-                            return vl::launch_adjoint_sweep(axis, L.cap_idx, d, subs, coef, w,
-                                                            (const float *)(aws + A.raw[axis]),
-                                                            (double *)(aws + A.part) + A.part_off[li], st);
-                        }))
-                        return r;
-                }
+            for (const RevLaunch &v : rev) {
+                const Launch &L = *v.L;
+                vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
+                                  L.count, L.total_tiles, 0};
+                double *part = (double *)(aws + A.part) + v.part_off;
+                if (int r = timed(ctx, VL_K_ADJ_X + v.axis, [&] {
+                        return v.lanes ? vl::launch_adjoint_xl(L.cap_idx, d, subs, ctx->at<float>(ctx->o_xl32), w,
+                                                               (const float *)(aws + A.raw[0]), part, st)
+                                       : vl::launch_adjoint_sweep(v.axis, L.cap_idx, d, subs, coef, w,
+                                                                  (const float *)(aws + A.raw[v.axis]), part, st);
+                    }))
+                    return r;
+            }
             if (int r = drain()) return r;
         }
     }
     // each tile summed its own contributions over all steps; add the tiles
     // of every volume in tile order
-    for (size_t li = 0; li < ctx->launches.size(); ++li) {
-        const Launch &L = ctx->launches[li];
+    for (const RevLaunch &v : rev) {
+        const Launch &L = *v.L;
         vl::SweepLaunch d{ctx->at<int>(ctx->o_itable) + L.ids_off, ctx->at<int>(ctx->o_itable) + L.prefix_off,
                           L.count, L.total_tiles, 0};
         if (int r = timed(ctx, VL_K_ADJ_REDUCE, [&] {
-                return vl::launch_reduce_partials(d, L.axis, (const double *)(aws + A.part) + A.part_off[li],
+                return vl::launch_reduce_partials(d, v.axis, (const double *)(aws + A.part) + v.part_off,
                                                   (double *)(aws + A.totals), st);
             }))
             return r;

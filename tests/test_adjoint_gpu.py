@@ -135,6 +135,30 @@ def test_adjoint_checkpoint_spacing_is_exact():
             assert np.array_equal(g[key], ref[key]), (ckpt, key)
 
 
+@pytest.mark.parametrize("x_lanes", [1, 2])
+def test_adjoint_x_lanes_reverse_batch_and_checkpoints(x_lanes):
+    """Reverse x solves with the lanes along the line next to split ones: a
+    batch of x-lines of 150, 100, 70 and 40 voxels (lanes for 129+, or 65+
+    with setting 2; split below), against the oracle, and bitwise equal for
+    every checkpoint spacing."""
+    specs, targets = [], []
+    for k, shape in enumerate([(150, 5, 6), (100, 7, 4), (70, 6, 5), (40, 9, 3)]):
+        s, t = _case(950 + k, shape, n_sub=1 + k % 2, bc="mixed", n_cells=20 + 5 * k)
+        specs.append(s)
+        targets.append(t)
+    n_steps = 4
+    res = [_oracle_grads(s, t, O.DECAY_ONCE, n_steps) for s, t in zip(specs, targets)]
+    finals = [r for _, r in res]
+    ref = _gpu_grads(specs, finals, O.DECAY_ONCE, n_steps, ckpt=1, x_lanes=x_lanes)
+    for k, (o, _) in enumerate(res):
+        _compare(ref[k], o, f"x lanes {x_lanes} sim {k}")
+    for ckpt in (2, 3, 4):
+        g = _gpu_grads(specs, finals, O.DECAY_ONCE, n_steps, ckpt=ckpt, x_lanes=x_lanes)
+        for k in range(len(specs)):
+            for key in ref[k]:
+                assert np.array_equal(g[k][key], ref[k][key]), (x_lanes, ckpt, k, key)
+
+
 def test_adjoint_zero_steps_and_out_of_domain_cell():
     spec, target = _case(31, (12, 11, 10))
     spec.cells.pos[5] = np.array(spec.lo) - 5.0
