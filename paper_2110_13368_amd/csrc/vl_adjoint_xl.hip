@@ -144,23 +144,7 @@ adjoint_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restri
     };
 
     double s_k = 0.0, s_sig = 0.0, s_lam = 0.0;
-    int j = row0 % ny, k = row0 / ny;
-    float wn[K], yn[K];  // the next line, loaded while this one is solved
-    axl_load<K>(wn, rw, line_off(row0, row0 < nrows));
-    axl_load<K>(yn, ry, line_off(row0, row0 < nrows));
-    for (int g = 0; g < kLines; ++g) {
-        const int row = row0 + g;
-        if (row >= nrows) break;  // wave-uniform
-        float r[K], y[K];
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-            r[t] = wn[t];
-            y[t] = yn[t];
-        }
-        const bool want = g + 1 < kLines && row + 1 < nrows;
-        axl_load<K>(wn, rw, line_off(row + 1, want));
-        axl_load<K>(yn, ry, line_off(row + 1, want));
-
+    auto reverse_line = [&](const int row, const int j, const int k, float (&r)[K], const float (&y)[K]) {
         // P_D^T on the input
         const int on = (j == 0 ? 1 << 2 : 0) | (j == ny - 1 ? 1 << 3 : 0) | (k == 0 ? 1 << 4 : 0) |
                        (k == nz - 1 ? 1 << 5 : 0);
@@ -235,9 +219,34 @@ adjoint_xl(SweepLaunch L, const SubDev *__restrict__ subs, const float *__restri
             o[t] = z ? 0.f : o[t];
         }
         axl_store<K>(o, rw, line_off(row, true), cnt, full);
-        if (++j == ny) {
-            j = 0;
-            ++k;
+    };
+    // A ring of three line slots (w and y), unrolled so that each slot has
+    // fixed registers: before line l is reversed, the loads of line l + 2 go
+    // into the slot that line l - 1 used.
+    constexpr int kAhead = 2, NS = kAhead + 1;
+    int j = row0 % ny, k = row0 / ny;
+    float rw_[NS][K], ry_[NS][K];
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a) {
+        const bool want = a < kLines && row0 + a < nrows;
+        axl_load<K>(rw_[a], rw, line_off(row0 + a, want));
+        axl_load<K>(ry_[a], ry, line_off(row0 + a, want));
+    }
+    for (int g = 0; g < kLines; g += NS) {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            const int row = row0 + g + a;
+            const int nrow = row + kAhead;
+            const bool want = g + a + kAhead < kLines && nrow < nrows;
+            axl_load<K>(rw_[(a + kAhead) % NS], rw, line_off(nrow, want));
+            axl_load<K>(ry_[(a + kAhead) % NS], ry, line_off(nrow, want));
+            if (g + a < kLines && row < nrows) {  // wave-uniform
+                reverse_line(row, j, k, rw_[a], ry_[a]);
+                if (++j == ny) {
+                    j = 0;
+                    ++k;
+                }
+            }
         }
     }
 
