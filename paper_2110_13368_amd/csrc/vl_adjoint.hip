@@ -251,6 +251,7 @@ static hipError_t launch_adj_axis(int cap_idx, const SweepLaunch &L, const SubDe
     case 4: hipLaunchKernelGGL((adjoint_sweep<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, w, raw, part); break;
     case 5: hipLaunchKernelGGL((adjoint_sweep<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, w, raw, part); break;
     case 6: hipLaunchKernelGGL((adjoint_sweep<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, w, raw, part); break;
+    case 7: hipLaunchKernelGGL((adjoint_sweep<AXIS, kCaps[7]>), grid, block, 0, st, L, subs, coef, w, raw, part); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

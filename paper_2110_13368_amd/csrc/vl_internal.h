@@ -16,8 +16,10 @@ constexpr int kWave = 64;
 
 // Per-lane capacities (elements of one half line held in VGPRs) compiled for
 // the FP32 sweeps.  A sweep class uses the smallest one >= ceil((n-1)/2).
-constexpr int kNumCaps = 7;
-constexpr int kCaps[kNumCaps] = {32, 64, 96, 128, 160, 200, 256};
+// 100 serves lines of 194-201 voxels (200 is a common grid edge) without the
+// 28 spare registers and rows of the 128 class.
+constexpr int kNumCaps = 8;
+constexpr int kCaps[kNumCaps] = {32, 64, 96, 100, 128, 160, 200, 256};
 
 // x and y solves of one z-plane per workgroup (volumes whose plane fits in
 // LDS): four wave pairs; plane rows padded to an odd stride so that 64 lanes

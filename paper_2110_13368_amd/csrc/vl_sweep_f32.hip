@@ -435,6 +435,7 @@ static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *s
     case 4: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[4]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
     case 5: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[5]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
     case 6: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[6]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
+    case 7: hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[7]>), grid, block, 0, st, L, subs, coef, field, raw, src); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -454,6 +455,7 @@ hipError_t launch_step_persistent(int cap_idx, int grid, const StepQueue &Q, con
     case 4: hipLaunchKernelGGL(sweep_step_persistent<kCaps[4]>, g, b, 0, st, Q, subs, coef, field, src); break;
     case 5: hipLaunchKernelGGL(sweep_step_persistent<kCaps[5]>, g, b, 0, st, Q, subs, coef, field, src); break;
     case 6: hipLaunchKernelGGL(sweep_step_persistent<kCaps[6]>, g, b, 0, st, Q, subs, coef, field, src); break;
+    case 7: hipLaunchKernelGGL(sweep_step_persistent<kCaps[7]>, g, b, 0, st, Q, subs, coef, field, src); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -469,6 +471,7 @@ hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks)
     case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[4]>, 128, 0);
     case 5: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[5]>, 128, 0);
     case 6: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[6]>, 128, 0);
+    case 7: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_step_persistent<kCaps[7]>, 128, 0);
     default: return hipErrorInvalidValue;
     }
 }

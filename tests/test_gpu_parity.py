@@ -57,7 +57,8 @@ def test_fp64_tiny_grids(shape, bc, decay):
 # --------------------------------------------------------------------------
 # FP32 path: line lengths around every split and capacity boundary
 
-LINE_LENGTHS = [1, 2, 3, 4, 5, 63, 64, 65, 66, 127, 128, 129, 130, 131, 193, 257, 258, 321, 401, 513]
+LINE_LENGTHS = [1, 2, 3, 4, 5, 63, 64, 65, 66, 127, 128, 129, 130, 131, 193, 194, 199, 200, 201, 202, 203, 257, 258,
+                321, 401, 513]
 # x solve with lanes along the line: around every voxels-per-lane boundary
 X_LANE_LENGTHS = [1, 2, 3, 31, 63, 64, 65, 66, 127, 128, 129, 191, 192, 193, 200, 255, 256, 257,
                   319, 320, 321, 383, 384, 385, 400, 447, 448, 449, 511, 512, 513]
