@@ -168,6 +168,19 @@ int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout)
 int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V,
                     const double *S, const double *U, const double *rho_star,
                     int *n_out_of_domain);
+/* The same upload from arrays that are already in device memory (same
+ * layouts; the caller keeps ownership and the arrays are only read on the
+ * bound stream during the call), for cells that move or change between
+ * steps: the agents' mechanics can update them on the device and the
+ * re-binning (voxel index, sort, composites; the same kernels as above)
+ * needs no host copy.  The arrays are checked on the device first (volumes
+ * finite and > 0, rates finite and >= 0, targets finite); on a failed check
+ * it returns VL_E_ARG and the previous cells stay.  Synchronises the stream.
+ * Cells come from the moving agents of the paper's hybrid model (Eq. 1,
+ * section "Future Work" on moving cell secretion/uptake to the device). */
+int vl_upload_cells_dev(vl_ctx *ctx, int sim, int n, const double *pos, const double *V,
+                        const double *S, const double *U, const double *rho_star,
+                        int *n_out_of_domain);
 
 /* Advance every simulation by n_steps steps, asynchronously on the bound
  * stream.  With a non-null stream the step is captured once into a hipGraph

@@ -55,6 +55,7 @@ SIGNATURES = {
     "vl_set_field": (_i, [_vp, _i, _vp, _i, _i]),
     "vl_get_field": (_i, [_vp, _i, _vp, _i, _i]),
     "vl_upload_cells": (_i, [_vp, _i, _i, _dp, _dp, _dp, _dp, _dp, _ip]),
+    "vl_upload_cells_dev": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _ip]),
     "vl_step": (_i, [_vp, _i]),
     "vl_sync": (_i, [_vp]),
     "vl_mass": (_i, [_vp, _i, _dp]),
@@ -188,6 +189,17 @@ def vl_set_field(ctx, sim, src_ptr: int, src_is_device: bool, layout: int = VL_S
 def vl_get_field(ctx, sim, dst_ptr: int, dst_is_device: bool, layout: int = VL_SOA) -> None:
     _check(lib().vl_get_field(ctx, int(sim), _vp(dst_ptr), int(bool(dst_is_device)), int(layout)),
            "vl_get_field")
+
+
+def vl_upload_cells_dev(ctx, sim, n: int, pos_ptr: int, V_ptr: int, S_ptr: int, U_ptr: int, rs_ptr: int) -> int:
+    """Cell upload from device arrays (raw pointers: pos n x 3, V n, S / U /
+    rho_star n x n_sub, float64, contiguous); returns the cells outside the
+    grid."""
+    n_out = C.c_int(0)
+    _check(lib().vl_upload_cells_dev(ctx, int(sim), int(n), C.c_void_p(pos_ptr), C.c_void_p(V_ptr),
+                                     C.c_void_p(S_ptr), C.c_void_p(U_ptr), C.c_void_p(rs_ptr), C.byref(n_out)),
+           "vl_upload_cells_dev")
+    return n_out.value
 
 
 def vl_upload_cells(ctx, sim, pos, V, S, U, rho_star, n_sub: int) -> int:
@@ -356,6 +368,22 @@ class Context:
     def upload_cells(self, k: int, cells) -> int:
         return vl_upload_cells(self.h, k, cells.pos, cells.V, cells.S, cells.U, cells.rho_star,
                                self.sims[k].n_sub)
+
+    def upload_cells_device(self, k: int, pos, V, S, U, rho_star) -> int:
+        """Cells from torch tensors on this context's device (float64: pos
+        (n, 3), V (n,), S / U / rho_star (n, n_sub)); the tensors must stay
+        alive until the call returns (it synchronises)."""
+        torch = self.torch
+        ts = [t.contiguous() for t in (pos, V, S, U, rho_star)]
+        for t in ts:
+            if t.device != self.device or t.dtype != torch.float64:
+                raise ValueError("cell tensors must be float64 on the context's device")
+        n = int(ts[1].numel())
+        if tuple(ts[0].shape) != (n, 3) or any(tuple(t.shape) != (n, self.sims[k].n_sub) for t in ts[2:]):
+            raise ValueError("cell tensor shapes do not match")
+        if self.stream is not None:  # the tensors were written on the caller's stream
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        return vl_upload_cells_dev(self.h, k, n, *[t.data_ptr() for t in ts])
 
     # -- stepping and diagnostics --
     def step(self, n: int = 1) -> None:

@@ -695,4 +695,31 @@ hipError_t launch_aos_to_soa(const void *src, void *field, int is_f64, long long
     return hipGetLastError();
 }
 
+// Checks cell arrays that are already on the device before an upload uses
+// them: bit 0 of *bad for a volume that is not finite and > 0, bit 1 for a
+// negative or non-finite rate, bit 2 for a non-finite target density.  The
+// flags are combined with atomic OR in global memory.
+__global__ void check_cells_kernel(int n, int ns, const double *__restrict__ V, const double *__restrict__ S,
+                                   const double *__restrict__ U, const double *__restrict__ RS, int *__restrict__ bad)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)n * ns) return;
+    const int i = (int)(g / ns);
+    int b = 0;
+    if (g % ns == 0 && !(V[i] > 0.0 && isfinite(V[i]))) b |= 1;
+    if (!(S[g] >= 0.0 && isfinite(S[g])) || !(U[g] >= 0.0 && isfinite(U[g]))) b |= 2;
+    if (!isfinite(RS[g])) b |= 4;
+    if (b) atomicOr(bad, b);
+}
+
+hipError_t launch_check_cells(int n, int ns, const double *V, const double *S, const double *U, const double *RS,
+                              int *bad, hipStream_t st)
+{
+    const long long total = (long long)n * ns;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(check_cells_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, ns, V, S, U, RS,
+                       bad);
+    return hipGetLastError();
+}
+
 }  // namespace vl

@@ -15,6 +15,9 @@
 using vl::SubDev;
 
 namespace vl {
+// checks of cell arrays already on the device (vl_kernels.hip)
+hipError_t launch_check_cells(int n, int ns, const double *V, const double *S, const double *U, const double *RS,
+                              int *bad, hipStream_t st);
 // the adjoint's reverse x solve with the lanes along the line (vl_adjoint_xl.hip)
 hipError_t launch_adjoint_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *w,
                              const float *raw, double *part, hipStream_t st);
@@ -1094,8 +1097,10 @@ int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout)
     return field_copy(ctx, sim, nullptr, dst, dst_is_device, layout, 0);
 }
 
-int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
-                    const double *U, const double *rho_star, int *n_out_of_domain)
+// The cell upload, from host arrays (validated on the host) or from device
+// arrays (validated on the device before anything changes).
+static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
+                        const double *U, const double *rho_star, int *n_out_of_domain, bool on_device)
 {
     if (int rc = check_sim(ctx, sim)) return rc;
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
@@ -1107,14 +1112,27 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
     const size_t ns = (size_t)s.ns;
     if (n > 0) {
         if (!pos || !V || !S || !U || !rho_star) return fail(VL_E_ARG, "cell arrays must not be null");
-        for (int i = 0; i < n; ++i)
-            if (!(V[i] > 0) || !std::isfinite(V[i])) return fail(VL_E_ARG, "cell volumes must be finite and > 0");
-        for (size_t q = 0; q < (size_t)n * ns; ++q)
-            if (!(S[q] >= 0) || !(U[q] >= 0)) return fail(VL_E_ARG, "rates must be >= 0");
-        if (!finite_all(S, (size_t)n * ns) || !finite_all(U, (size_t)n * ns) ||
-            !finite_all(rho_star, (size_t)n * ns))
-            return fail(VL_E_ARG, "rates and target densities must be finite");
+        if (on_device) {
+            int *flag = ctx->at<int>(ctx->o_counters) + 3;
+            int bad = 0;
+            VL_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+            VL_HIP(vl::launch_check_cells(n, (int)ns, V, S, U, rho_star, flag, ctx->stream));
+            VL_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            VL_HIP(hipStreamSynchronize(ctx->stream));
+            if (bad & 1) return fail(VL_E_ARG, "cell volumes must be finite and > 0");
+            if (bad & 2) return fail(VL_E_ARG, "rates must be finite and >= 0");
+            if (bad & 4) return fail(VL_E_ARG, "rates and target densities must be finite");
+        } else {
+            for (int i = 0; i < n; ++i)
+                if (!(V[i] > 0) || !std::isfinite(V[i])) return fail(VL_E_ARG, "cell volumes must be finite and > 0");
+            for (size_t q = 0; q < (size_t)n * ns; ++q)
+                if (!(S[q] >= 0) || !(U[q] >= 0)) return fail(VL_E_ARG, "rates must be >= 0");
+            if (!finite_all(S, (size_t)n * ns) || !finite_all(U, (size_t)n * ns) ||
+                !finite_all(rho_star, (size_t)n * ns))
+                return fail(VL_E_ARG, "rates and target densities must be finite");
+        }
     }
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     drop_graph(ctx);
     hipStream_t st = ctx->stream;
     s.n_cells = n;
@@ -1127,11 +1145,11 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
         if (n_out_of_domain) *n_out_of_domain = 0;
         return upload_cell_tables(ctx);
     }
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_V, V, sizeof(double) * n, hipMemcpyHostToDevice, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_S, S, sizeof(double) * n * ns, hipMemcpyHostToDevice, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_U, U, sizeof(double) * n * ns, hipMemcpyHostToDevice, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_RS, rho_star, sizeof(double) * n * ns, hipMemcpyHostToDevice, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_pos, pos, sizeof(double) * 3 * n, kind, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_V, V, sizeof(double) * n, kind, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_S, S, sizeof(double) * n * ns, kind, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_U, U, sizeof(double) * n * ns, kind, st));
+    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_RS, rho_star, sizeof(double) * n * ns, kind, st));
     int *counters = ctx->at<int>(ctx->o_counters);
     VL_HIP(hipMemsetAsync(counters, 0, sizeof(int) * 4, st));
     const int n_pad = next_pow2(n);
@@ -1181,6 +1199,18 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
     s.n_out = n_out;
     if (n_out_of_domain) *n_out_of_domain = n_out;
     return upload_cell_tables(ctx);
+}
+
+int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
+                    const double *U, const double *rho_star, int *n_out_of_domain)
+{
+    return upload_cells(ctx, sim, n, pos, V, S, U, rho_star, n_out_of_domain, false);
+}
+
+int vl_upload_cells_dev(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
+                        const double *U, const double *rho_star, int *n_out_of_domain)
+{
+    return upload_cells(ctx, sim, n, pos, V, S, U, rho_star, n_out_of_domain, true);
 }
 
 int vl_step(vl_ctx *ctx, int n_steps)

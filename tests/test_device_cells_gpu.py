@@ -1,0 +1,137 @@
+"""Cell upload from device arrays (vl_upload_cells_dev): cells that move
+between steps are re-binned on the device without a host copy.
+
+The upload runs the same binning as the host entry point (voxel of each cell
+in FP64, stable sort by voxel, composites of each occupied voxel in FP64), so
+fields after uploads from the host and from the device are bitwise equal;
+with the cells moving every few steps both are checked against the FP64
+oracle given the same sequence of uploads (Eq. 1 with the agents' positions
+changing between diffusion steps, as in the paper's hybrid model).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2110_13368_amd import binding as vb
+from paper_2110_13368_amd import workloads as W
+from tests.gpu_helpers import assert_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _spec(shape, n_sub, bc, n_cells, seed):
+    rng = np.random.default_rng(W.SEED_BASE + 1200 + seed)
+    h = (20.0, 20.0, 20.0)
+    return W.make_sim(rng, shape, h, n_sub, dtype="f32", bc=bc, n_cells=n_cells, cell_layout="gaussian",
+                      sigma=0.25 * min(n * d for n, d in zip(shape, h)))
+
+
+def _moves(spec, n_moves, seed):
+    """Cell positions after each move: a seeded random walk of a few voxels,
+    some cells leaving the grid, drawn up front so that every path sees the
+    same positions."""
+    rng = np.random.default_rng(seed)
+    pos = spec.cells.pos.copy()
+    out = []
+    for _ in range(n_moves):
+        pos = pos + rng.normal(scale=1.5 * spec.h[0], size=pos.shape)
+        out.append(pos.copy())
+    return out
+
+
+def _device(ctx, a):
+    return ctx.torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(ctx.device)
+
+
+def _run(specs, moves, every, n_steps, from_device, x_lanes):
+    ctx = vb.Context(specs, device="cuda:0")
+    try:
+        ctx.set_option(vb.VL_OPT_X_LANES, x_lanes)
+        for k, s in enumerate(specs):
+            ctx.set_field(k, s.rho0)
+        outs = []
+        done = 0
+        for m in range(len(moves[0]) + 1):
+            if m > 0:
+                for k, s in enumerate(specs):
+                    c = s.cells
+                    if from_device:
+                        n_out = ctx.upload_cells_device(k, _device(ctx, moves[k][m - 1]), _device(ctx, c.V),
+                                                        _device(ctx, c.S), _device(ctx, c.U),
+                                                        _device(ctx, c.rho_star))
+                    else:
+                        n_out = ctx.upload_cells(k, W.Cells(pos=moves[k][m - 1], V=c.V, S=c.S, U=c.U,
+                                                            rho_star=c.rho_star))
+                    outs.append(n_out)
+            take = min(every, n_steps - done)
+            ctx.step(take)
+            done += take
+        ctx.sync()
+        return [ctx.get_field(k).astype(np.float64) for k in range(len(specs))], outs
+    finally:
+        ctx.close()
+
+
+def _oracle(spec, moves, every, n_steps):
+    sim = O.from_spec(spec)
+    done = 0
+    for m in range(len(moves) + 1):
+        if m > 0:
+            c = spec.cells
+            sim.upload_cells(moves[m - 1], c.V, c.S, c.U, c.rho_star)
+        take = min(every, n_steps - done)
+        sim.step(take)
+        done += take
+    return sim.get_field()
+
+
+@pytest.mark.parametrize("x_lanes", [0, 1])
+def test_moving_cells_uploaded_from_device(x_lanes):
+    specs = [_spec((140, 12, 9), 2, "mixed", 300, 1), _spec((33, 20, 17), 1, "neumann", 150, 2)]
+    every, n_moves = 3, 3
+    moves = [_moves(s, n_moves, 77 + k) for k, s in enumerate(specs)]
+    n_steps = every * (n_moves + 1)
+    fd, out_d = _run(specs, moves, every, n_steps, True, x_lanes)
+    fh, out_h = _run(specs, moves, every, n_steps, False, x_lanes)
+    assert out_d == out_h
+    assert any(o > 0 for o in out_d)  # the walk takes some cells off the grid
+    for k, spec in enumerate(specs):
+        assert np.array_equal(fd[k], fh[k]), f"sim {k}: device and host uploads differ"
+        assert_close(fd[k], _oracle(spec, moves[k], every, n_steps), 1e-5, f"moving cells sim {k}")
+
+
+def test_device_upload_rejects_bad_cells_and_keeps_the_old_ones():
+    spec = _spec((20, 10, 8), 2, "neumann", 50, 3)
+    ctx = vb.Context([spec], device="cuda:0")
+    try:
+        ctx.set_field(0, spec.rho0)
+        c = spec.cells
+        ctx.step(2)
+        ref = ctx.get_field(0).copy()
+        for bad in ("V", "S", "rho_star"):
+            V, S, rs = c.V.copy(), c.S.copy(), c.rho_star.copy()
+            if bad == "V":
+                V[7] = 0.0
+            elif bad == "S":
+                S[3, 1] = -1.0
+            else:
+                rs[5, 0] = np.nan
+            with pytest.raises(vb.VoxlodError) as e:
+                ctx.upload_cells_device(0, _device(ctx, c.pos), _device(ctx, V), _device(ctx, S),
+                                        _device(ctx, c.U), _device(ctx, rs))
+            assert e.value.code == vb.VL_E_ARG
+        # the cells of the first upload are still in place: stepping on gives
+        # the same field as a context that never saw the bad uploads
+        ctx.step(2)
+        got = ctx.get_field(0)
+    finally:
+        ctx.close()
+    ctx2 = vb.Context([spec], device="cuda:0")
+    try:
+        ctx2.set_field(0, spec.rho0)
+        ctx2.step(4)
+        want = ctx2.get_field(0)
+    finally:
+        ctx2.close()
+    assert not np.array_equal(ref, got)
+    assert np.array_equal(got, want)
