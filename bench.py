@@ -100,6 +100,40 @@ def time_steps(ctx, steps: int, warmup: int):
     return time.perf_counter() - t0
 
 
+def time_moving_cells(ctx, wl, steps: int, every: int):
+    """Steps with the cells of every simulation moved and re-binned from device
+    arrays every `every` steps (vl_upload_cells_dev: voxel index, sort,
+    composites; the positions are prepared on the device beforehand, a small
+    random walk per move).  Returns (seconds, uploads, host seconds in the
+    upload calls, which include waiting for the steps queued before them)."""
+    import torch
+    n_moves = max(steps // every, 1)
+    g = torch.Generator(device=ctx.device).manual_seed(211013368 + 50)
+    dev = []
+    for s in wl.sims:
+        c = s.cells
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(ctx.device)
+        pos0 = t(c.pos)
+        walk = torch.randn((n_moves,) + tuple(pos0.shape), generator=g, device=ctx.device,
+                           dtype=torch.float64) * (0.5 * s.h[0])
+        dev.append((pos0 + torch.cumsum(walk, 0), t(c.V), t(c.S), t(c.U), t(c.rho_star)))
+    torch.cuda.synchronize()
+    t_up = 0.0
+    t0 = time.perf_counter()
+    done = 0
+    for m in range(n_moves):
+        u0 = time.perf_counter()
+        for k, (pos, V, S, U, rs) in enumerate(dev):
+            ctx.upload_cells_device(k, pos[m], V, S, U, rs)
+        t_up += time.perf_counter() - u0
+        take = min(every, steps - done)
+        ctx.step(take)
+        done += take
+    ctx.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, n_moves, t_up
+
+
 def kernel_profile(ctx, steps: int):
     """Per-kernel totals over `steps` directly launched steps, from HIP events
     recorded on the library's stream around every launch."""
@@ -277,6 +311,8 @@ def main():
                          "0 split solve")
     ap.add_argument("--x-lane-lines", default="auto", choices=["auto", "1", "2", "4", "8", "16"],
                     help="force the x-lines per wave of the lanes-along-the-line solve (after tuning)")
+    ap.add_argument("--move-cells-every", type=int, default=0,
+                    help="also time steps with the cells moved and re-binned on the device every N steps")
     ap.add_argument("--sources", default="auto", choices=["auto", "0", "1", "2"],
                     help="force where cell sources are applied (after tuning): 0 own kernel, 1 in the z sweep, "
                          "2 carried into the next x solve")
@@ -330,6 +366,15 @@ def main():
     print(f"bench: {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
 
     stats = kernel_profile(ctx, args.steps)
+    moving = None
+    if args.move_cells_every > 0 and precision == vb.VL_F32 and any(s.cells.n > 0 for s in wl.sims):
+        t_mv, n_up, t_up = time_moving_cells(ctx, wl, args.steps, args.move_cells_every)
+        moving = {"every_steps": args.move_cells_every, "steps": args.steps, "uploads": n_up,
+                  "value": E * args.steps / t_mv, "unit": "voxel-substrate updates/s",
+                  "ms_per_rebinning": round(1e3 * (t_mv - elapsed) / n_up, 3),
+                  "note": "cells moved on the device and re-binned (vl_upload_cells_dev) every every_steps steps, "
+                          "inside the timed loop; value counts the diffusion updates only; ms_per_rebinning is the "
+                          "loop's time beyond the same steps with fixed cells, per upload"}
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -408,6 +453,8 @@ def main():
         "kernels": kernels,
     }
     line.update(extra)
+    if moving is not None:
+        line["moving_cells"] = moving
     if not args.no_copy_reference:
         line["copy_reference"] = [copy_reference(128 << 20), copy_reference(2 << 30, reps=5)]
     if not args.no_cpu_baseline:
