@@ -1,6 +1,6 @@
 """Benchmark of the LOD diffusion-decay step with cell sources on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config single|tumour|batched|plain|adjoint]
+    python bench.py [--steps K] [--warmup W] [--config single|tumour|batched|planar|plain|adjoint]
 
 A step is one full LOD step (x, y, z line solves with Dirichlet projection and
 decay folded in, then the cell sources) over every simulation of the
@@ -84,6 +84,8 @@ def make_workload(name: str):
         return W.batched()
     if name == "plain":
         return W.plain_fp64()
+    if name == "planar":
+        return W.planar()
     raise SystemExit(f"unknown config {name!r}")
 
 
@@ -362,7 +364,9 @@ def main():
     elapsed = time_steps(ctx, args.steps, args.warmup)
     value = E * args.steps / elapsed
     esize = 8 if precision == vb.VL_F64 else 4
-    b_alg = 3 * 2 * esize  # bytes per voxel-substrate-step: three sweeps, read + write
+    # grids one voxel thick (2-D) take two sweeps: their z solve is the identity
+    e_thin = sum(sp.n_vox * sp.n_sub for sp in wl.sims if sp.shape[2] == 1) if precision == vb.VL_F32 else 0
+    b_alg = 2 * esize * (3 * E - e_thin) / E  # bytes per voxel-substrate-step: the sweeps' read + write
     print(f"bench: {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
 
     stats = kernel_profile(ctx, args.steps)
@@ -389,6 +393,8 @@ def main():
         alg_bytes = 2 * esize * e_plane  # x and y of those volumes: one read and one write
     elif dom in ("sweep_x", "sweep_y") and fused_xy:
         alg_bytes = 2 * esize * (E - e_plane)  # the volumes whose planes do not fit
+    elif dom == "sweep_z":
+        alg_bytes = 2 * esize * (E - e_thin)  # the volumes more than one voxel thick
     elif dom.startswith("sweep"):
         alg_bytes = 2 * esize * E  # every element read once and written once per sweep
     elif dom == "step":
@@ -443,8 +449,9 @@ def main():
                    "xy_per_plane": fused_xy, "cell_sources": fuse_src, "xcd_order": xcd_ord,
                    "x_lanes_along_line": x_lanes, "x_lanes_min_line": {0: None, 1: 129, 2: 65}[x_lanes_opt],
                    "x_lines_per_wave": x_lane_lines},
-        "hbm_effective": {"basis": "B_alg: three sweeps x (read + write) per voxel-substrate-step; with x and y "
-                                   "solved per z-plane the step moves less than B_alg",
+        "hbm_effective": {"basis": "B_alg: three sweeps (two on grids one voxel thick) x (read + write) per "
+                                   "voxel-substrate-step; with x and y solved per z-plane the step moves less "
+                                   "than B_alg",
                           "bytes_per_update": b_alg,
                           "bytes_moved_per_update": (b_alg - 2 * esize * e_plane / E) if fused_xy else b_alg,
                           "GBps": round(b_alg * value / 1e9, 1),

@@ -549,6 +549,39 @@ __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims
     *p = (*p + ab.x) * ab.y;
 }
 
+// The same update for the simulations one voxel thick in z, whose z solve is
+// the identity when the decay is applied once and is therefore not launched:
+// no z tile applies their sources, so this pass does, after the y solve's
+// stores (which already hold the last Dirichlet projection).  skip_carried:
+// leave those whose sources the next x solve applies.
+__global__ void sources_thin_f32_kernel(const SimCells *__restrict__ cells, int nsims,
+                                        const int *__restrict__ occ_prefix, int total_occ,
+                                        const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
+                                        const float2 *__restrict__ comp, float *__restrict__ field, int skip_carried)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (j >= total_occ) return;
+    const int sim = find_slot_i(occ_prefix, nsims, j);
+    const SimCells &C = cells[sim];
+    if (s >= C.ns || subs[C.sub0].n[2] != 1 || (skip_carried && C.xs_base >= 0)) return;
+    const int jl = j - occ_prefix[sim];
+    const int v = occ_vox[C.occ_base + jl];
+    const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
+    float *p = field + subs[C.sub0 + s].base + v;
+    *p = (*p + ab.x) * ab.y;
+}
+
+hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+                                   int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
+                                   float *field, int skip_carried, hipStream_t st)
+{
+    if (total_occ <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_thin_f32_kernel, dim3((total_occ + 255) / 256, max_ns), dim3(256), 0, st,
+                       cells, nsims, occ_prefix, total_occ, subs, occ_vox, comp, field, skip_carried);
+    return hipGetLastError();
+}
+
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
                               int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
                               float *field, int only_carried, hipStream_t st)

@@ -18,6 +18,11 @@ namespace vl {
 // checks of cell arrays already on the device (vl_kernels.hip)
 hipError_t launch_check_cells(int n, int ns, const double *V, const double *S, const double *U, const double *RS,
                               int *bad, hipStream_t st);
+// cell sources of the simulations one voxel thick, whose z solve is not
+// launched (vl_kernels.hip)
+hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+                                   int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
+                                   float *field, int skip_carried, hipStream_t st);
 // the adjoint's reverse x solve with the lanes along the line (vl_adjoint_xl.hip)
 hipError_t launch_adjoint_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *w,
                              const float *raw, double *part, hipStream_t st);
@@ -264,6 +269,16 @@ int timed(vl_ctx *ctx, int kind, F &&launch)
 
 // ---- one step ------------------------------------------------------------
 
+// A volume one voxel thick in z (a two-dimensional simulation) has z-lines of
+// one voxel, whose solve divides by 1 + sigma: with the decay applied once
+// (sigma = 0) that is the identity, and the Dirichlet projection after it
+// repeats the one the y solve stored, so its z solve is not launched (FP32
+// path) and its cell sources are applied by a pass of their own.
+bool z_skipped(const vl_ctx *ctx, int q, int axis)
+{
+    return axis == 2 && ctx->precision == VL_F32 && ctx->decay == VL_DECAY_ONCE && ctx->subs[q].n[2] == 1;
+}
+
 // Whether the steps of this context carry the cell sources of eligible
 // simulations into the next step's x solve (VL_OPT_FUSE_SOURCES 2).
 bool carries(const vl_ctx *ctx)
@@ -360,6 +375,19 @@ int enqueue_step(vl_ctx *ctx, int phase)
             }
             for (const Launch &L : ctx->launches)
                 if (L.axis == axis && (rc = sweep(L))) return rc;
+        }
+        // sources of the volumes whose z solve is skipped
+        bool thin = false;
+        for (const SimHost &s : ctx->sims)
+            thin = thin || (s.n_occ > 0 && z_skipped(ctx, s.sub0, 2));
+        if (fused && thin) {
+            rc = timed(ctx, VL_K_SOURCES, [&] {
+                return vl::launch_sources_thin_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
+                                                   ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns, subs,
+                                                   ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp),
+                                                   field, phase != kStepWhole ? 1 : 0, st);
+            });
+            if (rc) return rc;
         }
         }
         if (total_occ > 0 && !fused) {
@@ -641,6 +669,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
             std::vector<std::vector<int>> groups(vl::kNumCaps);
             for (int q = 0; q < nsubs; ++q) {
                 const int n = ctx->subs[q].n[axis];
+                if (z_skipped(ctx, q, axis)) continue;
                 const int ci = cap_index(n - 1 - (n - 1) / 2);
                 if (ci < 0)
                     return fail(VL_E_SHAPE, "FP32 path: lines longer than " +

@@ -131,6 +131,25 @@ def gaussian_positions(rng, n, sigma, centre, lo, hi) -> np.ndarray:
     return p
 
 
+def disc_positions(rng, n, sigma, centre, lo, hi) -> np.ndarray:
+    """Gaussian disc in x and y (width sigma about the centre), uniform in z
+    through the grid's thickness; redrawn until every cell is inside."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+
+    def draw(m):
+        q = rng.normal(centre, sigma, size=(m, 3))
+        q[:, 2] = rng.uniform(lo[2], hi[2], size=m)
+        return q
+
+    p = draw(n)
+    bad = ~_inside(p, lo, hi)
+    while bad.any():
+        p[bad] = draw(int(bad.sum()))
+        bad = ~_inside(p, lo, hi)
+    return p
+
+
 def tumour_rates(rng, n, n_sub) -> Tuple[np.ndarray, ...]:
     """Per-cell rates as in the single large simulation: S, U log-uniform in
     [0.1, 10] /min, rho* uniform in [0, 40], V uniform in [1000, 4000] um^3."""
@@ -150,8 +169,9 @@ def make_sim(rng, shape, h, n_sub, *, D=None, lam=None, dt=0.01, dtype="f32",
     bc: "neumann" (all zero flux), "dirichlet" (all faces Dirichlet with a value
     drawn from rho_range), or "mixed" (each (substrate, face) Dirichlet with
     probability p_dirichlet).  cell_layout: "uniform", "gaussian" (ball of
-    width sigma about the centre) or "core" (core_fraction Gaussian, the rest
-    uniform)."""
+    width sigma about the centre), "core" (core_fraction Gaussian, the rest
+    uniform) or "disc" (Gaussian in x and y, uniform in z: for grids one voxel
+    thick)."""
     shape = tuple(int(v) for v in shape)
     h = tuple(float(v) for v in h)
     lo = centred_lo(shape, h) if lo is None else tuple(float(v) for v in lo)
@@ -176,6 +196,8 @@ def make_sim(rng, shape, h, n_sub, *, D=None, lam=None, dt=0.01, dtype="f32",
             pos = uniform_positions(rng, n_cells, lo, hi)
         elif cell_layout == "gaussian":
             pos = gaussian_positions(rng, n_cells, sigma, centre, lo, hi)
+        elif cell_layout == "disc":
+            pos = disc_positions(rng, n_cells, sigma, centre, lo, hi)
         elif cell_layout == "core":
             n_core = int(round(core_fraction * n_cells))
             pos = np.concatenate([gaussian_positions(rng, n_core, sigma, centre, lo, hi),
@@ -266,10 +288,26 @@ def tumour_scale(scale: float = 1.0, dtype="f32") -> Workload:
                     "1e6 cells, 70% Gaussian core + 30% uniform")
 
 
+def planar(n_sims: int = 32, edge: int = 512, dtype="f32") -> Workload:
+    """A batch of n_sims two-dimensional simulations (grids edge x edge x 1 of
+    10 um voxels: x and y solves only), 4 substrates each (D log-uniform
+    [1e3, 1e5], lambda log-uniform [1e-3, 1]), zero-flux faces, rho0 i.i.d.
+    U[0, 40]; 1e4 cells per simulation in a Gaussian disc (sigma 800 um);
+    dt = 0.01, 200 steps."""
+    sims = []
+    for k in range(n_sims):
+        rng = rng_for(6, k)
+        sims.append(make_sim(rng, (edge, edge, 1), (10.0, 10.0, 10.0), 4, dtype=dtype, bc="neumann",
+                             n_cells=10000, cell_layout="disc", sigma=800.0 * edge / 512))
+    return Workload(f"planar-{n_sims}x{edge}^2x4-{dtype}", sims, 200, dtype,
+                    "two-dimensional tissue sections, Gaussian disc of cells")
+
+
 CONFIGS = {
     "plain": plain_fp64,
     "single": single_large,
     "batched": batched,
     "adjoint": differentiation,
     "tumour": tumour_scale,
+    "planar": planar,
 }

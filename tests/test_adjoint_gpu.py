@@ -110,6 +110,22 @@ def test_adjoint_long_lines_and_degenerate_axes(mode):
         _compare(g, o, f"{shape} mode {mode}")
 
 
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+@pytest.mark.parametrize("shape,h,x_lanes", [((150, 40, 1), (10.0, 15.0, 10.0), 1),
+                                             ((31, 70, 1), (20.0, 20.0, 20.0), 0),
+                                             ((24, 18, 13), (8.0, 20.0, 35.0), 0),
+                                             ((140, 9, 6), (12.0, 5.0, 30.0), 1)])
+def test_adjoint_two_dimensional_and_unequal_edges(mode, shape, h, x_lanes):
+    # grids one voxel thick (2-D) and voxels with unequal edges
+    spec, target = _case(321 + sum(shape), shape, bc="mixed", n_cells=30, h=h)
+    if shape[2] == 1:
+        spec.bc_kind[:, 4:] = 0
+        spec.bc_value[:, 4:] = 0.0
+    o, r = _oracle_grads(spec, target, mode, 6)
+    g = _gpu_grads([spec], [r], mode, 6, ckpt=4, x_lanes=x_lanes)[0]
+    _compare(g, o, f"{shape} h={h} mode {mode}")
+
+
 def test_adjoint_batched_ragged():
     specs, targets = [], []
     for k, shape in enumerate([(20, 13, 9), (33, 8, 17), (7, 7, 40)]):

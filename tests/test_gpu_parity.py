@@ -7,6 +7,8 @@ accuracy target set for FP32 storage and sweeps over 100 steps.  The paper's
 own Method 2 (section "Methods of Validation") is this voxel-by-voxel
 cross-check of the GPU field against the CPU field.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -94,6 +96,68 @@ def test_fp32_boundary_mixes_and_decay(bc, decay, x_lanes):
     (got,), _ = run_gpu([spec], 30, decay=decay[0], x_lanes=x_lanes)
     want = run_oracle(spec, 30, decay[1])
     assert_close(got, want, 1e-5, f"fp32 {bc}")
+
+
+# --------------------------------------------------------------------------
+# two-dimensional grids and unequal voxel edges.  A 2-D simulation is a grid
+# one voxel thick with no z faces: its z-lines hold one voxel each, so the z
+# solve reduces to the identity (decay once) or to the z share of the decay
+# (decay in thirds), and the step is the x and y solves of the 2-D method.
+
+def _planar(shape, bc, n_cells, seed, h=(20.0, 20.0, 20.0)):
+    rng = np.random.default_rng(W.SEED_BASE + 700 + seed)
+    spec = W.make_sim(rng, shape, h, 2, dtype="f32", bc=bc, n_cells=n_cells, cell_layout="disc",
+                      sigma=0.25 * min(shape[0] * h[0], shape[1] * h[1]))
+    spec.bc_kind[:, 4:] = 0  # a 2-D grid has no z faces
+    spec.bc_value[:, 4:] = 0.0
+    if n_cells >= 3:
+        spec.cells.pos[1] = spec.cells.pos[0]
+        spec.cells.pos[2] = np.array(spec.lo) - 3.0
+    return spec
+
+
+PLANAR = [((300, 250, 1), "mixed"), ((513, 64, 1), "dirichlet"), ((64, 513, 1), "mixed"),
+          ((1, 300, 1), "neumann"), ((130, 1, 1), "mixed"), ((200, 199, 1), "neumann")]
+
+
+@pytest.mark.parametrize("x_lanes", [0, 1, 2])
+@pytest.mark.parametrize("decay", DECAYS)
+@pytest.mark.parametrize("shape,bc", PLANAR)
+def test_fp32_two_dimensional(shape, bc, decay, x_lanes):
+    spec = _planar(shape, bc, 200, sum(shape) + len(bc), h=(10.0, 15.0, 10.0))
+    (got,), n_out = run_gpu([spec], 50, decay=decay[0], x_lanes=x_lanes)
+    assert n_out == [1]
+    assert_close(got, run_oracle(spec, 50, decay[1]), 1e-5, f"2-D {shape} {bc}")
+
+
+@pytest.mark.parametrize("sources_mode", [0, 1, 2])
+def test_fp32_two_dimensional_in_a_batch_with_3d(sources_mode):
+    """2-D and 3-D simulations in one ragged batch, with every placement of
+    the cell sources (own kernel, in the z solve, carried into the next x)."""
+    specs = [_planar((260, 180, 1), "mixed", 400, 1), _spec((70, 40, 21), 2, "mixed", 300, "f32", 5),
+             _planar((129, 7, 1), "dirichlet", 30, 2), _planar((40, 90, 1), "neumann", 80, 3)]
+    fields, _ = run_gpu(specs, 40, x_lanes=1, sources_mode=sources_mode)
+    for k, spec in enumerate(specs):
+        assert_close(fields[k], run_oracle(spec, 40), 1e-5, f"batch sim {k} {spec.shape}")
+
+
+@pytest.mark.parametrize("x_lanes", [0, 1, 2])
+@pytest.mark.parametrize("decay", DECAYS)
+def test_fp32_unequal_voxel_edges(decay, x_lanes):
+    """Voxels of 8 x 20 x 35 um: a different coupling dt D / h^2 on each axis."""
+    spec = _spec((140, 70, 33), 2, "mixed", 500, "f32", 91, layout="gaussian", h=(8.0, 20.0, 35.0))
+    (got,), _ = run_gpu([spec], 40, decay=decay[0], x_lanes=x_lanes)
+    assert_close(got, run_oracle(spec, 40, decay[1]), 1e-5, "unequal edges")
+
+
+@pytest.mark.parametrize("decay", DECAYS)
+def test_fp64_two_dimensional_and_unequal_edges(decay):
+    specs = [_planar((90, 70, 1), "mixed", 60, 4, h=(10.0, 30.0, 5.0)),
+             _spec((20, 15, 12), 2, "dirichlet", 40, "f64", 17, h=(5.0, 12.0, 40.0))]
+    specs[0] = dataclasses.replace(specs[0], rho0=specs[0].rho0.astype(np.float64))
+    fields, _ = run_gpu(specs, 10, precision=vb.VL_F64, decay=decay[0])
+    for k, spec in enumerate(specs):
+        assert_close(fields[k], run_oracle(spec, 10, decay[1]), 1e-12, f"fp64 sim {k} {spec.shape}")
 
 
 @pytest.mark.parametrize("x_lanes", [0, 1, 2])

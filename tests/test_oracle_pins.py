@@ -311,6 +311,57 @@ def test_cell_voxel_mapping_brute_force():
 
 
 # --------------------------------------------------------------------------
+# P12: a grid one voxel thick is the two-dimensional method (x and y solves
+# only, section "Elements of Parallelism"): its z-lines hold one voxel, whose
+# solve is the identity when the decay is applied once and the z share of the
+# decay when it is split in thirds.  Written with SciPy's banded solver line by
+# line, independent of the oracle and of the dense Kronecker reference.
+
+def _banded_zero_flux_solve(u, c, sigma, axis):
+    from scipy.linalg import solve_banded
+    n = u.shape[axis]
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -c
+    ab[2, :-1] = -c
+    ab[1, :] = 1.0 + sigma + 2.0 * c
+    if n > 1:
+        ab[1, 0] -= c
+        ab[1, -1] -= c
+    else:
+        ab[1, 0] = 1.0 + sigma
+    moved = np.moveaxis(u, axis, 0)
+    return np.moveaxis(solve_banded((1, 1), ab, moved.reshape(n, -1)).reshape(moved.shape), 0, axis)
+
+
+@pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
+def test_one_voxel_thick_grid_is_the_2d_method(mode):
+    nx, ny = 41, 29
+    h = (10.0, 25.0, 10.0)
+    D = np.array([3e4, 800.0])
+    lam = np.array([0.5, 0.02])
+    dt = 0.05
+    sim = make((nx, ny, 1), D, lam, dt=dt, h=h, mode=mode)
+    rng = np.random.default_rng(1212)
+    rho = rng.uniform(0.0, 40.0, size=(2, 1, ny, nx))
+    sim.set_field(rho)
+    steps = 4
+    sim.step(steps)
+    want = rho[:, 0].copy()  # (sub, y, x)
+    for _ in range(steps):
+        for s in range(2):
+            cx, cy = dt * D[s] / h[0] ** 2, dt * D[s] / h[1] ** 2
+            sig = dt * lam[s] / 3.0 if mode == O.DECAY_THIRDS else 0.0
+            u = _banded_zero_flux_solve(want[s], cx, sig, axis=1)
+            if mode == O.DECAY_ONCE:
+                u = u / (1.0 + dt * lam[s])
+            u = _banded_zero_flux_solve(u, cy, sig, axis=0)
+            if mode == O.DECAY_THIRDS:
+                u = u / (1.0 + sig)
+            want[s] = u
+    assert rel(sim.get_field()[:, 0], want) < 1e-13
+
+
+# --------------------------------------------------------------------------
 # P11: results do not depend on the thread count; stepping is resumable.
 
 def test_thread_count_and_resume_bitwise():
