@@ -376,10 +376,11 @@ int enqueue_step(vl_ctx *ctx, int phase)
             for (const Launch &L : ctx->launches)
                 if (L.axis == axis && (rc = sweep(L))) return rc;
         }
-        // sources of the volumes whose z solve is skipped
+        // sources of the volumes whose z solve is skipped, unless the next x
+        // solve applies them
         bool thin = false;
         for (const SimHost &s : ctx->sims)
-            thin = thin || (s.n_occ > 0 && z_skipped(ctx, s.sub0, 2));
+            thin = thin || (s.n_occ > 0 && z_skipped(ctx, s.sub0, 2) && (phase == kStepWhole || s.xs_base < 0));
         if (fused && thin) {
             rc = timed(ctx, VL_K_SOURCES, [&] {
                 return vl::launch_sources_thin_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
