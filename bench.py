@@ -102,6 +102,38 @@ def time_steps(ctx, steps: int, warmup: int):
     return time.perf_counter() - t0
 
 
+def time_snapshots(ctx, wl, steps: int, every: int):
+    """Steps with a snapshot of every simulation's field to pinned host memory
+    every `every` steps (vl_snapshot: a staging copy on the library's stream,
+    the transfer on its copy stream while the next steps run), all waited for
+    at the end.  Returns (seconds, snapshots, seconds for one snapshot of
+    every simulation taken alone, bytes per snapshot of all simulations)."""
+    torch = ctx.torch
+    outs = [torch.empty(tuple(s.field_shape), dtype=ctx.dtype, pin_memory=True) for s in wl.sims]
+    nbytes = sum(o.numel() * o.element_size() for o in outs)
+    for rep in range(2):  # the first call also creates the copy stream
+        ctx.sync()
+        t0 = time.perf_counter()
+        for k in range(len(wl.sims)):
+            ctx.snapshot(k, outs[k])
+        ctx.snapshot_wait()
+        t_alone = time.perf_counter() - t0
+    ctx.sync()
+    t0 = time.perf_counter()
+    done = n = 0
+    while done < steps:
+        take = min(every, steps - done)
+        ctx.step(take)
+        done += take
+        if take == every:
+            for k in range(len(wl.sims)):
+                ctx.snapshot(k, outs[k])
+            n += 1
+    ctx.sync()
+    ctx.snapshot_wait()
+    return time.perf_counter() - t0, n, t_alone, nbytes
+
+
 def time_moving_cells(ctx, wl, steps: int, every: int):
     """Steps with the cells of every simulation moved and re-binned from device
     arrays every `every` steps (vl_upload_cells_dev: voxel index, sort,
@@ -313,6 +345,8 @@ def main():
                          "0 split solve")
     ap.add_argument("--x-lane-lines", default="auto", choices=["auto", "1", "2", "4", "8", "16"],
                     help="force the x-lines per wave of the lanes-along-the-line solve (after tuning)")
+    ap.add_argument("--snapshot-every", type=int, default=0,
+                    help="also time the steps with a snapshot of the field to pinned host memory every N steps")
     ap.add_argument("--move-cells-every", type=int, default=0,
                     help="also time steps with the cells moved and re-binned on the device every N steps")
     ap.add_argument("--sources", default="auto", choices=["auto", "0", "1", "2"],
@@ -379,6 +413,18 @@ def main():
                   "note": "cells moved on the device and re-binned (vl_upload_cells_dev) every every_steps steps, "
                           "inside the timed loop; value counts the diffusion updates only; ms_per_rebinning is the "
                           "loop's time beyond the same steps with fixed cells, per upload"}
+    snaps = None
+    if args.snapshot_every > 0:
+        t_sn, n_sn, t_alone, sn_bytes = time_snapshots(ctx, wl, args.steps, args.snapshot_every)
+        snaps = {"every_steps": args.snapshot_every, "steps": args.steps, "snapshots": n_sn,
+                 "value": E * args.steps / t_sn, "unit": "voxel-substrate updates/s",
+                 "bytes_per_snapshot": sn_bytes,
+                 "ms_per_snapshot_beyond_steps": round(1e3 * (t_sn - elapsed) / max(n_sn, 1), 3),
+                 "transfer_alone_ms": round(1e3 * t_alone, 3),
+                 "transfer_alone_GBps": round(sn_bytes / t_alone / 1e9, 1),
+                 "note": "every simulation's field copied to pinned host memory every every_steps steps inside "
+                         "the timed loop (vl_snapshot); ms_per_snapshot_beyond_steps is the loop's time beyond "
+                         "the same steps without snapshots; transfer_alone is one snapshot with nothing to overlap"}
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -462,6 +508,8 @@ def main():
     line.update(extra)
     if moving is not None:
         line["moving_cells"] = moving
+    if snaps is not None:
+        line["snapshots"] = snaps
     if not args.no_copy_reference:
         line["copy_reference"] = [copy_reference(128 << 20), copy_reference(2 << 30, reps=5)]
     if not args.no_cpu_baseline:

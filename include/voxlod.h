@@ -159,6 +159,26 @@ int vl_volume_stride(vl_ctx *ctx, int sim, size_t *elems);
 int vl_set_field(vl_ctx *ctx, int sim, const void *src, int src_is_device, int layout);
 int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout);
 
+/* Snapshots of one simulation's field while stepping goes on (section
+ * "GPU-accelerated Long-time Simulations": long runs that save the full data
+ * at fixed simulated-time intervals).  vl_snapshot enqueues, on the bound
+ * stream after the work already queued there, a copy of simulation sim's
+ * field into the caller's device buffer stage_dev, then a copy from there
+ * into host_dst on a copy stream of the library's own, so the steps enqueued
+ * afterwards run while the transfer goes on.  Both buffers hold
+ * n_sub*nz*ny*nx elements of the context's precision in layout VL_SOA
+ * (substrate-major, x fastest), the caller owns them, and they stay in use
+ * until vl_snapshot_wait returns.  host_dst should be pinned (hipHostMalloc)
+ * for the transfer to overlap the steps; with pageable memory the transfer
+ * may complete before the call returns.  Each call orders its staging copy
+ * after the previous call's transfer, so one staging buffer can serve every
+ * snapshot.  vl_snapshot_wait blocks until every snapshot enqueued so far is
+ * in host memory.  Not for use under stream capture.
+ * Errors: VL_E_ARG (sim out of range, null buffer), VL_E_STATE (not bound),
+ * VL_E_HIP. */
+int vl_snapshot(vl_ctx *ctx, int sim, void *stage_dev, void *host_dst);
+int vl_snapshot_wait(vl_ctx *ctx);
+
 /* Upload n cells of one simulation (host arrays, row-major): pos n x 3 (um),
  * V n (um^3, > 0), S, U n x n_sub (1/min, >= 0), rho_star n x n_sub.  The
  * order is the order of application.  On the device: voxel of each cell

@@ -56,6 +56,8 @@ SIGNATURES = {
     "vl_get_field": (_i, [_vp, _i, _vp, _i, _i]),
     "vl_upload_cells": (_i, [_vp, _i, _i, _dp, _dp, _dp, _dp, _dp, _ip]),
     "vl_upload_cells_dev": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _ip]),
+    "vl_snapshot": (_i, [_vp, _i, _vp, _vp]),
+    "vl_snapshot_wait": (_i, [_vp]),
     "vl_step": (_i, [_vp, _i]),
     "vl_sync": (_i, [_vp]),
     "vl_mass": (_i, [_vp, _i, _dp]),
@@ -191,6 +193,16 @@ def vl_get_field(ctx, sim, dst_ptr: int, dst_is_device: bool, layout: int = VL_S
            "vl_get_field")
 
 
+def vl_snapshot(ctx, sim, stage_ptr: int, host_ptr: int) -> None:
+    """Enqueue a snapshot of one simulation's field: device staging buffer and
+    host destination, each n_sub*nz*ny*nx elements (raw pointers)."""
+    _check(lib().vl_snapshot(ctx, int(sim), _vp(stage_ptr), _vp(host_ptr)), "vl_snapshot")
+
+
+def vl_snapshot_wait(ctx) -> None:
+    _check(lib().vl_snapshot_wait(ctx), "vl_snapshot_wait")
+
+
 def vl_upload_cells_dev(ctx, sim, n: int, pos_ptr: int, V_ptr: int, S_ptr: int, U_ptr: int, rs_ptr: int) -> int:
     """Cell upload from device arrays (raw pointers: pos n x 3, V n, S / U /
     rho_star n x n_sub, float64, contiguous); returns the cells outside the
@@ -316,6 +328,8 @@ class Context:
             vl_bind(self.h, self.field.data_ptr(), self.workspace.data_ptr(), self.stream.cuda_stream)
             self.offsets = [vl_field_offset(self.h, k) for k in range(len(self.sims))]
             self.strides = [vl_volume_stride(self.h, k) for k in range(len(self.sims))]
+            self._stages = {}      # per simulation: device staging buffer of its snapshots
+            self._snap_keep = []   # host buffers of snapshots not yet waited for
             if set_initial:
                 for k, s in enumerate(self.sims):
                     self.set_field(k, s.rho0)
@@ -354,6 +368,30 @@ class Context:
         out = np.empty(s.field_shape, dtype=self.np_dtype)
         vl_get_field(self.h, k, out.ctypes.data, False, VL_SOA)
         return out
+
+    def snapshot(self, k: int, out=None):
+        """Enqueue a copy of simulation k's field to host memory after the
+        steps queued so far; steps enqueued afterwards overlap the transfer.
+        ``out``: a contiguous CPU tensor of shape (n_sub, nz, ny, nx) and the
+        field's dtype, pinned for the transfer to overlap (a pinned one is
+        allocated when None).  Its contents are valid after snapshot_wait()."""
+        torch = self.torch
+        shape = tuple(self.sims[k].field_shape)
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, pin_memory=True)
+        elif (tuple(out.shape) != shape or out.dtype != self.dtype or out.device.type != "cpu"
+              or not out.is_contiguous()):
+            raise ValueError("snapshot buffer must be a contiguous CPU tensor of the field's shape and dtype")
+        stage = self._stages.get(k)
+        if stage is None:
+            stage = self._stages[k] = torch.empty(shape, dtype=self.dtype, device=self.device)
+        vl_snapshot(self.h, k, stage.data_ptr(), out.data_ptr())
+        self._snap_keep.append(out)
+        return out
+
+    def snapshot_wait(self) -> None:
+        vl_snapshot_wait(self.h)
+        self._snap_keep.clear()
 
     def field_view(self, k: int):
         """Torch view (n_sub, nz, ny, nx) of one simulation's volumes."""

@@ -172,6 +172,11 @@ struct vl_ctx {
 
     bool profiling = false;
     std::vector<hipEvent_t> pool;
+    // snapshots: transfers to the host on a stream of their own
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t snap_staged = nullptr;  // staging copy done (bound stream)
+    hipEvent_t snap_done = nullptr;    // last transfer done (copy stream)
+    bool snap_pending = false;
     std::vector<Rec> recs;
     long long k_launches[VL_K_COUNT] = {0};
     double k_ms[VL_K_COUNT] = {0};
@@ -523,6 +528,12 @@ int vl_destroy(vl_ctx *ctx)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->copy_stream) {
+        (void)hipStreamSynchronize(ctx->copy_stream);
+        (void)hipStreamDestroy(ctx->copy_stream);
+    }
+    if (ctx->snap_staged) (void)hipEventDestroy(ctx->snap_staged);
+    if (ctx->snap_done) (void)hipEventDestroy(ctx->snap_done);
     delete ctx;
     return VL_OK;
 }
@@ -1125,6 +1136,39 @@ int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout)
 {
     if (!dst) return fail(VL_E_ARG, "dst is null");
     return field_copy(ctx, sim, nullptr, dst, dst_is_device, layout, 0);
+}
+
+int vl_snapshot(vl_ctx *ctx, int sim, void *stage_dev, void *host_dst)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
+    if (!stage_dev || !host_dst) return fail(VL_E_ARG, "stage_dev and host_dst must not be null");
+    if (!ctx->copy_stream) {
+        VL_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+        VL_HIP(hipEventCreateWithFlags(&ctx->snap_staged, hipEventDisableTiming));
+        VL_HIP(hipEventCreateWithFlags(&ctx->snap_done, hipEventDisableTiming));
+    }
+    const SimHost &s = ctx->sims[sim];
+    const size_t nv = (size_t)s.nvox(), es = ctx->esize;
+    hipStream_t st = ctx->stream;
+    // the staging buffer may still be on its way to the host
+    if (ctx->snap_pending) VL_HIP(hipStreamWaitEvent(st, ctx->snap_done, 0));
+    VL_HIP(hipMemcpy2DAsync(stage_dev, nv * es, (const char *)ctx->field + s.field_off * es, s.vol_stride * es,
+                            nv * es, s.ns, hipMemcpyDeviceToDevice, st));
+    VL_HIP(hipEventRecord(ctx->snap_staged, st));
+    VL_HIP(hipStreamWaitEvent(ctx->copy_stream, ctx->snap_staged, 0));
+    VL_HIP(hipMemcpyAsync(host_dst, stage_dev, nv * es * s.ns, hipMemcpyDeviceToHost, ctx->copy_stream));
+    VL_HIP(hipEventRecord(ctx->snap_done, ctx->copy_stream));
+    ctx->snap_pending = true;
+    return VL_OK;
+}
+
+int vl_snapshot_wait(vl_ctx *ctx)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (ctx->copy_stream) VL_HIP(hipStreamSynchronize(ctx->copy_stream));
+    ctx->snap_pending = false;
+    return VL_OK;
 }
 
 // The cell upload, from host arrays (validated on the host) or from device

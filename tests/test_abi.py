@@ -84,6 +84,9 @@ def test_setup_validation_and_sizes():
         assert _code(vb.vl_bind, h, 256, 4, 0) == vb.VL_E_ARG  # misaligned
         assert _code(vb.vl_step, h, 1) == vb.VL_E_STATE  # not bound
         assert _code(vb.vl_upload_cells, h, 0, [[0, 0, 0]], [1.0], [[1, 1]], [[1, 1]], [[1, 1]], 2) == vb.VL_E_STATE
+        assert _code(vb.vl_snapshot, h, 0, 256, 256) == vb.VL_E_STATE  # not bound
+        assert _code(vb.vl_snapshot, h, 2, 256, 256) == vb.VL_E_ARG  # no such simulation
+        vb.vl_snapshot_wait(h)  # nothing enqueued: returns at once
     finally:
         vb.vl_destroy(h)
 

@@ -1,0 +1,94 @@
+"""Snapshots of the field to host memory while stepping goes on (vl_snapshot,
+vl_snapshot_wait): the long runs of the paper's section "GPU-accelerated
+Long-time Simulations" save the full data at fixed simulated-time intervals.
+
+A snapshot enqueued after step t holds the field after step t, bitwise,
+although the steps enqueued after it run while it travels to the host:
+checked against get_field of a second context stepped to t, and against the
+FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2110_13368_amd import binding as vb
+from paper_2110_13368_amd import workloads as W
+from tests.gpu_helpers import assert_close, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _spec(shape, n_sub, bc, n_cells, seed, dtype="f32"):
+    rng = np.random.default_rng(W.SEED_BASE + 1300 + seed)
+    return W.make_sim(rng, shape, (20.0, 20.0, 20.0), n_sub, dtype=dtype, bc=bc, n_cells=n_cells,
+                      cell_layout="uniform")
+
+
+def _reference(specs, times, precision):
+    """Fields of every simulation after each of the given step counts."""
+    ctx = vb.Context(specs, precision=precision, device="cuda:0")
+    out = {}
+    try:
+        done = 0
+        for t in sorted(set(times)):
+            ctx.step(t - done)
+            done = t
+            out[t] = [ctx.get_field(k) for k in range(len(specs))]
+    finally:
+        ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", [vb.VL_F32, vb.VL_F64])
+def test_snapshots_hold_the_field_of_their_step(precision):
+    dtype = "f32" if precision == vb.VL_F32 else "f64"
+    specs = [_spec((70, 33, 12), 2, "mixed", 200, 1, dtype), _spec((25, 40, 30), 3, "neumann", 100, 2, dtype)]
+    # (steps before the snapshot, simulation); simulation 0's staging buffer
+    # serves three snapshots, and two snapshots follow each other directly
+    plan = [(3, 0), (4, 1), (2, 0), (0, 1), (6, 0)]
+    ctx = vb.Context(specs, precision=precision, device="cuda:0")
+    torch = ctx.torch
+    taken = []
+    try:
+        t = 0
+        for i, (n, k) in enumerate(plan):
+            ctx.step(n)
+            t += n
+            out = None
+            if i == 3:  # one pageable host buffer
+                out = torch.empty(tuple(specs[k].field_shape), dtype=ctx.dtype)
+            taken.append((t, k, ctx.snapshot(k, out)))
+        ctx.step(5)  # runs while the last transfers go on
+        t_end = t + 5
+        ctx.snapshot_wait()
+        snaps = [(t, k, o.numpy().copy()) for t, k, o in taken]
+        final = [ctx.get_field(k) for k in range(len(specs))]
+    finally:
+        ctx.close()
+    ref = _reference(specs, [t for t, _, _ in snaps] + [t_end], precision)
+    for t, k, a in snaps:
+        assert np.array_equal(a, ref[t][k]), f"snapshot of sim {k} after {t} steps"
+    for k in range(len(specs)):
+        assert np.array_equal(final[k], ref[t_end][k])
+    tol = 1e-5 if precision == vb.VL_F32 else 1e-12
+    for t, k, a in snaps[:2]:
+        assert_close(a.astype(np.float64), run_oracle(specs[k], t), tol, f"snapshot sim {k} step {t}")
+
+
+def test_snapshot_rejects_bad_arguments():
+    spec = _spec((20, 10, 8), 1, "neumann", 10, 3)
+    ctx = vb.Context([spec], device="cuda:0")
+    try:
+        with pytest.raises(vb.VoxlodError) as e:
+            vb.vl_snapshot(ctx.h, 0, 0, 0)
+        assert e.value.code == vb.VL_E_ARG
+        with pytest.raises(vb.VoxlodError) as e:
+            vb.vl_snapshot(ctx.h, 1, 256, 256)  # no such simulation: refused before any copy
+        assert e.value.code == vb.VL_E_ARG
+        with pytest.raises(ValueError):
+            ctx.snapshot(0, ctx.torch.empty((2, 3), dtype=ctx.dtype))
+        ctx.step(2)
+        a = ctx.snapshot(0)
+        ctx.snapshot_wait()
+        assert np.array_equal(a.numpy(), ctx.get_field(0))
+    finally:
+        ctx.close()
