@@ -74,6 +74,29 @@ def test_snapshots_hold_the_field_of_their_step(precision):
         assert_close(a.astype(np.float64), run_oracle(specs[k], t), tol, f"snapshot sim {k} step {t}")
 
 
+@pytest.mark.parametrize("sources_mode", [0, 1, 2])
+def test_snapshots_with_every_source_placement(sources_mode):
+    """With the sources carried into the next x solve, every step call ends
+    with a pass that applies the last step's sources, so a snapshot between
+    calls holds the complete field."""
+    specs = [_spec((150, 20, 9), 2, "mixed", 300, 4), _spec((40, 30, 20), 1, "neumann", 80, 5)]
+    ctx = vb.Context(specs, device="cuda:0")
+    try:
+        ctx.set_option(vb.VL_OPT_X_LANES, 1)
+        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, sources_mode)
+        ctx.step(4)
+        a = [ctx.snapshot(k) for k in range(2)]
+        ctx.step(3)
+        b = ctx.snapshot(0)
+        ctx.step(2)
+        ctx.snapshot_wait()
+    finally:
+        ctx.close()
+    for k in range(2):
+        assert_close(a[k].numpy().astype(np.float64), run_oracle(specs[k], 4), 1e-5, f"sim {k} step 4")
+    assert_close(b.numpy().astype(np.float64), run_oracle(specs[0], 7), 1e-5, "sim 0 step 7")
+
+
 def test_snapshot_rejects_bad_arguments():
     spec = _spec((20, 10, 8), 1, "neumann", 10, 3)
     ctx = vb.Context([spec], device="cuda:0")
