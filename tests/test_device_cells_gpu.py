@@ -135,3 +135,36 @@ def test_device_upload_rejects_bad_cells_and_keeps_the_old_ones():
         ctx2.close()
     assert not np.array_equal(ref, got)
     assert np.array_equal(got, want)
+
+
+def test_cell_counts_change_by_orders_of_magnitude():
+    """Uploads of 3000, 30, 0, 3 and 3000 cells (within the capacity reserved
+    at set-up) between steps, from device arrays, in every source placement;
+    each stretch checked against the oracle given the same uploads."""
+    spec = _spec((150, 16, 11), 2, "mixed", 3000, 4)
+    c = spec.cells
+    counts = [30, 0, 3, 3000]
+    rng = np.random.default_rng(99)
+    subsets = [np.sort(rng.choice(c.n, size=m, replace=False)) for m in counts]
+    for mode in (0, 1, 2):
+        ctx = vb.Context([spec], device="cuda:0")
+        sim = O.from_spec(spec)
+        try:
+            ctx.set_option(vb.VL_OPT_X_LANES, 1)
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, mode)
+            ctx.set_field(0, spec.rho0)
+            ctx.step(3)
+            sim.step(3)
+            for idx in subsets:
+                n_out = ctx.upload_cells_device(0, _device(ctx, c.pos[idx].reshape(-1, 3)),
+                                                _device(ctx, c.V[idx]), _device(ctx, c.S[idx].reshape(-1, 2)),
+                                                _device(ctx, c.U[idx].reshape(-1, 2)),
+                                                _device(ctx, c.rho_star[idx].reshape(-1, 2)))
+                assert n_out == sim.upload_cells(c.pos[idx].reshape(-1, 3), c.V[idx], c.S[idx].reshape(-1, 2),
+                                                  c.U[idx].reshape(-1, 2), c.rho_star[idx].reshape(-1, 2))
+                ctx.step(4)
+                sim.step(4)
+                assert_close(ctx.get_field(0).astype(np.float64), sim.get_field(), 1e-5,
+                             f"mode {mode}, {len(idx)} cells")
+        finally:
+            ctx.close()
