@@ -43,3 +43,20 @@ def test_named_config_shapes():
     lo, hi = np.array(s.lo), np.array(s.lo) + np.array(s.shape) * np.array(s.h)
     assert np.all((s.cells.pos >= lo) & (s.cells.pos < hi))
     assert np.all((s.D >= 1e3) & (s.D <= 1e5)) and np.all((s.lam >= 1e-3) & (s.lam <= 1.0))
+
+
+def test_planar_config_is_two_dimensional():
+    p = W.planar(n_sims=3)
+    assert len(p.sims) == 3 and p.voxel_substrates == 3 * 512 * 512 * 4
+    for sim in p.sims:
+        assert sim.shape == (512, 512, 1) and sim.n_sub == 4 and sim.cells.n == 10000
+        assert np.all(sim.bc_kind == 0)
+        lo, hi = np.array(sim.lo), np.array(sim.lo) + np.array(sim.shape) * np.array(sim.h)
+        assert np.all((sim.cells.pos >= lo) & (sim.cells.pos < hi))
+        # a disc: Gaussian in x and y about the centre, uniform through the thickness
+        c = 0.5 * (lo + hi)
+        assert abs(np.std(sim.cells.pos[:, 0] - c[0]) - 800.0) < 40.0
+        assert abs(np.mean(sim.cells.pos[:, 2] - c[2])) < 0.2
+    q = W.planar(n_sims=3)
+    assert np.array_equal(p.sims[2].cells.pos, q.sims[2].cells.pos)
+    assert not np.array_equal(p.sims[0].cells.pos, p.sims[1].cells.pos)
