@@ -530,7 +530,19 @@ __device__ __forceinline__ int find_slot_i(const int *__restrict__ prefix, int c
     return lo;
 }
 
-// FP32: one thread per (occupied voxel, substrate); rho <- (rho + A) * (1/B).
+// The composite of occupied voxel jl (of simulation C) on substrate s:
+// rho <- (rho + A) * (1/B).
+__device__ __forceinline__ void apply_composite(const SimCells &C, int jl, int s, const SubDev *__restrict__ subs,
+                                                const int *__restrict__ occ_vox, const float2 *__restrict__ comp,
+                                                float *__restrict__ field)
+{
+    const int v = occ_vox[C.occ_base + jl];
+    const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
+    float *p = field + subs[C.sub0 + s].base + v;
+    *p = (*p + ab.x) * ab.y;
+}
+
+// FP32: one thread per (occupied voxel, substrate).
 __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims,
                                    const int *__restrict__ occ_prefix, int total_occ,
                                    const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
@@ -542,11 +554,7 @@ __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns || (only_carried && C.xs_base < 0)) return;
-    const int jl = j - occ_prefix[sim];
-    const int v = occ_vox[C.occ_base + jl];
-    const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
-    float *p = field + subs[C.sub0 + s].base + v;
-    *p = (*p + ab.x) * ab.y;
+    apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox, comp, field);
 }
 
 // The same update for the simulations one voxel thick in z, whose z solve is
@@ -565,11 +573,7 @@ __global__ void sources_thin_f32_kernel(const SimCells *__restrict__ cells, int 
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns || subs[C.sub0].n[2] != 1 || (skip_carried && C.xs_base >= 0)) return;
-    const int jl = j - occ_prefix[sim];
-    const int v = occ_vox[C.occ_base + jl];
-    const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
-    float *p = field + subs[C.sub0 + s].base + v;
-    *p = (*p + ab.x) * ab.y;
+    apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox, comp, field);
 }
 
 hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
