@@ -393,10 +393,12 @@ def test_thread_count_and_resume_bitwise():
 # L = 1/2 |rho_T - target|^2 a central difference along any direction is
 # exact up to rounding; parameters are checked with central differences.
 
-def _adjoint_case(mode, bc="mixed"):
+def _adjoint_case(mode, bc="mixed", shape=(5, 4, 6), h=(20.0, 20.0, 20.0)):
     rng = np.random.default_rng(101 + mode)
-    spec = W.make_sim(rng, (5, 4, 6), (20.0, 20.0, 20.0), 2, dtype="f64", bc=bc, n_cells=6,
-                      cell_layout="uniform")
+    spec = W.make_sim(rng, shape, h, 2, dtype="f64", bc=bc, n_cells=6, cell_layout="uniform")
+    if shape[2] == 1:  # a 2-D grid has no z faces
+        spec.bc_kind[:, 4:] = 0
+        spec.bc_value[:, 4:] = 0.0
     spec.cells.pos[1] = spec.cells.pos[0]
     target = rng.uniform(0, 40, size=spec.field_shape)
     return spec, target
@@ -440,8 +442,11 @@ def test_adjoint_field_dot_product(mode):
 
 
 @pytest.mark.parametrize("mode", [O.DECAY_ONCE, O.DECAY_THIRDS])
-def test_adjoint_parameters_vs_central_differences(mode):
-    spec, target = _adjoint_case(mode)
+@pytest.mark.parametrize("shape,h", [((5, 4, 6), (20.0, 20.0, 20.0)), ((9, 7, 1), (10.0, 25.0, 10.0)),
+                                     ((5, 4, 6), (8.0, 20.0, 35.0))])
+def test_adjoint_parameters_vs_central_differences(mode, shape, h):
+    # cubic voxels, a 2-D grid, and voxels with unequal edges
+    spec, target = _adjoint_case(mode, shape=shape, h=h)
     n_steps = 5
     _, r = _loss(spec, target, mode, n_steps)
     g = O.from_spec(spec, decay_mode=mode).adjoint(n_steps, r)
