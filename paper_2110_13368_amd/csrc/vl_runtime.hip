@@ -1143,11 +1143,10 @@ int vl_snapshot(vl_ctx *ctx, int sim, void *stage_dev, void *host_dst)
     if (int rc = check_sim(ctx, sim)) return rc;
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (!stage_dev || !host_dst) return fail(VL_E_ARG, "stage_dev and host_dst must not be null");
-    if (!ctx->copy_stream) {
-        VL_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
-        VL_HIP(hipEventCreateWithFlags(&ctx->snap_staged, hipEventDisableTiming));
-        VL_HIP(hipEventCreateWithFlags(&ctx->snap_done, hipEventDisableTiming));
-    }
+    // created at the first snapshot (each only once, also after a failure)
+    if (!ctx->copy_stream) VL_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+    if (!ctx->snap_staged) VL_HIP(hipEventCreateWithFlags(&ctx->snap_staged, hipEventDisableTiming));
+    if (!ctx->snap_done) VL_HIP(hipEventCreateWithFlags(&ctx->snap_done, hipEventDisableTiming));
     const SimHost &s = ctx->sims[sim];
     const size_t nv = (size_t)s.nvox(), es = ctx->esize;
     hipStream_t st = ctx->stream;
