@@ -489,7 +489,7 @@ def main():
         "dtype": wl.dtype,
         "data": "synthetic (seeded generators shaped like the paper's tumour workloads)",
         "config": {"workload": wl.name, "sims": len(wl.sims), "voxel_substrates": E,
-                   "grid": list(wl.sims[0].shape) if len(wl.sims) == 1 else "ragged",
+                   "grid": (list(wl.sims[0].shape) if len({sp.shape for sp in wl.sims}) == 1 else "ragged"),
                    "n_sub": wl.sims[0].n_sub, "cells": int(sum(s.cells.n for s in wl.sims)),
                    "dt": wl.sims[0].dt, "parallelism": "single-gpu", "step_mode": mode,
                    "xy_per_plane": fused_xy, "cell_sources": fuse_src, "xcd_order": xcd_ord,
