@@ -106,22 +106,47 @@ extern "C" {
 
 typedef struct vl_ctx vl_ctx;
 
+/* Library plumbing (no passage of the paper defines these): the ABI version
+ * this header describes, and the message of the calling thread's last
+ * failure. */
 int vl_abi_version(void);
 const char *vl_last_error(void);
 
 /* Lifecycle.  n_sims >= 1 independent simulations share one context and are
- * stepped together (each launch covers all of them). */
+ * stepped together (each launch covers all of them).  Each simulation is one
+ * instance of Eq. (1) on its own voxel grid; running many at once serves the
+ * exploration and calibration runs of section "Introduction and Motivation"
+ * (many independent simulations of one model).  precision VL_F32 or VL_F64
+ * (section "Methods of Validation for Data Integrity", Method 2: the paper's
+ * field is double precision); decay_split VL_DECAY_ONCE or VL_DECAY_THIRDS
+ * (where the decay term of Eq. (1) enters the direction-by-direction solve,
+ * which the paper does not state).  *out receives the context; VL_E_ARG on
+ * a null out or a value out of range.  vl_destroy frees the host state
+ * (device memory stays the caller's); a null context is accepted. */
 int vl_create(vl_ctx **out, int n_sims, int precision, int decay_split);
 int vl_destroy(vl_ctx *ctx);
 
-/* Per-simulation setup (before vl_finalize).
- * vl_set_grid: nx, ny, nz >= 1 voxels of edges dx, dy, dz > 0 (um), lower
+/* Per-simulation setup (before vl_finalize; VL_E_STATE after it, VL_E_ARG
+ * for a simulation index out of range or a value out of its limits).
+ * vl_set_grid (Eq. (1) discretised on a uniform voxel grid, section "Elements
+ * of Parallelism": one substrate vector per voxel; section "Input Datasets":
+ * a cube domain of voxels): nx, ny, nz >= 1 voxels of edges dx, dy, dz > 0 (um), lower
  *   corner (x0, y0, z0).  Each volume must hold fewer than 2^28 voxels;
  *   the FP32 path takes lines of at most 513 voxels.
- * vl_set_substrates: n_sub >= 1, D[s] >= 0 (um^2/min), lambda[s] >= 0 (1/min).
- *   All faces start zero-flux.
- * vl_set_boundary: kind VL_NEUMANN or VL_DIRICHLET with a finite value.
- * vl_reserve_cells: capacity for vl_upload_cells (default 0, max 2^24). */
+ * vl_set_substrates (the diffusion coefficient D and decay rate lambda of
+ *   each substrate in Eq. (1)): n_sub >= 1, D[s] >= 0 (um^2/min),
+ *   lambda[s] >= 0 (1/min); the host arrays hold n_sub values each and are
+ *   copied.  All faces start zero-flux.
+ * vl_set_boundary (section "Elements of Parallelism": Dirichlet conditions
+ *   are applied by a function of their own around the direction solves;
+ *   section "Methods of Validation for Data Integrity", Method 3, where a
+ *   mistake in that function's index range showed in the images): face
+ *   0..5 = x-, x+, y-, y+, z-, z+ of substrate sub becomes VL_NEUMANN (zero
+ *   flux) or VL_DIRICHLET with a finite value, which overwrites the outermost
+ *   voxel layer of that face before the x solve and after each solve.
+ * vl_reserve_cells (the cells i of Eq. (1)'s source sum): capacity for
+ *   vl_upload_cells (default 0, max 2^24); it sizes the cell tables of the
+ *   workspace. */
 int vl_set_grid(vl_ctx *ctx, int sim, int nx, int ny, int nz, double dx, double dy,
                 double dz, double x0, double y0, double z0);
 int vl_set_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D,
@@ -131,11 +156,23 @@ int vl_reserve_cells(vl_ctx *ctx, int sim, int max_cells);
 
 /* Fix the layout for time step dt > 0 and report the sizes the caller must
  * allocate: *field_elems elements of the context's precision and
- * *workspace_bytes bytes (256-byte aligned device memory). */
+ * *workspace_bytes bytes (256-byte aligned device memory).  Section
+ * "Elements of Parallelism": the arrays the diffusion solves need besides the
+ * densities are set up once and stay on the device; here they are the line
+ * solve pivots, the launch tables and the cell tables, all placed in the one
+ * workspace.  Host-only: no device call.  VL_E_STATE if a simulation lacks a
+ * grid or substrates or the context is already finalized; VL_E_SHAPE if
+ * lines are too long for the FP32 path or the tables overflow. */
 int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_bytes);
 
 /* Attach device memory and a stream.  Computes the line-solve coefficients
- * on the device (FP64 arithmetic) and uploads the launch tables.  May be called
+ * on the device (FP64 arithmetic) and uploads the launch tables (section
+ * "Elements of Parallelism": the densities and the auxiliary arrays are
+ * copied to the device once and stay resident; the elimination constants of
+ * the line solves depend only on dt, D, lambda and the grid).  field_dev and
+ * workspace_dev are device pointers of the sizes vl_finalize reported,
+ * 256-byte aligned and owned by the caller (VL_E_ARG otherwise).  The field
+ * contents are left as they are.  Synchronises the stream.  May be called
  * again to move to other buffers or another stream; the workspace is then
  * re-initialised and cells must be uploaded again.  stream may be NULL
  * (the null stream; steps are then launched without a graph). */
@@ -150,12 +187,20 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream);
 int vl_update_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D,
                          const double *lambda);
 
+/* Where one simulation's volumes lie in the field (section "Elements of
+ * Parallelism" ports the paper's per-voxel density vectors to flat arrays;
+ * here each substrate is a volume of its own, x fastest): the element offset
+ * of substrate 0 and the element distance between substrates.  Host-only;
+ * VL_E_STATE before vl_finalize. */
 int vl_field_offset(vl_ctx *ctx, int sim, size_t *elem_offset);
 int vl_volume_stride(vl_ctx *ctx, int sim, size_t *elems);
 
 /* Copy one simulation's field in or out.  src/dst hold n_sub*nz*ny*nx elements
  * of the context's precision, host or device memory, in layout VL_SOA or
- * VL_AOS.  vl_get_field synchronises the stream. */
+ * VL_AOS (VL_AOS is the paper's voxel-major order of section "Elements of
+ * Parallelism"; reading the whole field back is how section "Methods of
+ * Validation for Data Integrity", Method 2, compares GPU and CPU results
+ * voxel by voxel).  Both synchronise the stream; the caller keeps src/dst. */
 int vl_set_field(vl_ctx *ctx, int sim, const void *src, int src_is_device, int layout);
 int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout);
 
@@ -179,12 +224,16 @@ int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout)
 int vl_snapshot(vl_ctx *ctx, int sim, void *stage_dev, void *host_dst);
 int vl_snapshot_wait(vl_ctx *ctx);
 
-/* Upload n cells of one simulation (host arrays, row-major): pos n x 3 (um),
+/* The cells of Eq. (1)'s source sum, whose secretion/uptake section "Future
+ * Work" names as the next part to run on the device.
+ * Upload n cells of one simulation (host arrays, row-major): pos n x 3 (um),
  * V n (um^3, > 0), S, U n x n_sub (1/min, >= 0), rho_star n x n_sub.  The
  * order is the order of application.  On the device: voxel of each cell
  * (FP64), stable sort by voxel, per occupied voxel the composite of its cells
  * (FP64 arithmetic).  *n_out_of_domain (may be NULL) receives the number of
- * cells outside the grid.  Synchronises the stream.  n = 0 removes all cells. */
+ * cells outside the grid.  Synchronises the stream.  n = 0 removes all cells.
+ * VL_E_SHAPE if n exceeds vl_reserve_cells' capacity; VL_E_ARG for a
+ * volume <= 0, a negative rate or a non-finite value (nothing changes then). */
 int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V,
                     const double *S, const double *U, const double *rho_star,
                     int *n_out_of_domain);
@@ -202,15 +251,26 @@ int vl_upload_cells_dev(vl_ctx *ctx, int sim, int n, const double *pos, const do
                         const double *S, const double *U, const double *rho_star,
                         int *n_out_of_domain);
 
-/* Advance every simulation by n_steps steps, asynchronously on the bound
- * stream.  With a non-null stream the step is captured once into a hipGraph
- * and replayed; the graph is rebuilt after any change of cells or binding. */
+/* Advance every simulation by n_steps steps of Eq. (1), asynchronously on the
+ * bound stream: per step the x, y and z line solves of section "Elements of
+ * Parallelism" (each line a tridiagonal elimination and back-substitution,
+ * with the Dirichlet function around them), then the cells' secretion/uptake
+ * (section "Future Work").  VL_E_STATE before vl_bind; n_steps < 0 is
+ * VL_E_ARG.  Faults of the launched kernels surface at vl_sync.  With a
+ * non-null stream the step is captured once into a hipGraph and replayed; the
+ * graph is rebuilt after any change of cells or binding. */
 int vl_step(vl_ctx *ctx, int n_steps);
+/* Wait for the work queued on the bound stream (plumbing).  VL_E_HIP carries
+ * a kernel fault; VL_E_STATE reports a one-launch step whose tile gave up
+ * waiting. */
 int vl_sync(vl_ctx *ctx);
 
 /* Diagnostics (synchronising).  vl_mass: out[s] = sum over voxels of rho (FP64
- * accumulation, deterministic order).  vl_check_finite: *bad = number of
- * non-finite field values (status VL_E_NONFINITE when > 0). */
+ * accumulation, deterministic order); with zero-flux faces and lambda = 0 the
+ * diffusion part of Eq. (1) conserves it, which is what the validation of
+ * section "Methods of Validation for Data Integrity" relies on.
+ * vl_check_finite: *bad = number of non-finite field values (status
+ * VL_E_NONFINITE when > 0).  out holds n_sub doubles (host, caller's). */
 int vl_mass(vl_ctx *ctx, int sim, double *out);
 int vl_check_finite(vl_ctx *ctx, long long *bad);
 
@@ -273,12 +333,17 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * the device), large ones keep more loads in flight per wave.  Fields do not
  * depend on it; vl_tune times the candidates. */
 #define VL_OPT_X_LANE_LINES 8
-/* Selecting VL_MODE_PERSISTENT currently fails with VL_E_STATE: the one-launch
+/* Launch-shape options (no passage of the paper defines them; fields do not
+ * depend on them beyond rounding, and the placements of the sources and the
+ * x+y-per-plane option give bitwise equal fields).  Unknown options and
+ * values out of range are VL_E_ARG.
+ * Selecting VL_MODE_PERSISTENT currently fails with VL_E_STATE: the one-launch
  * step is switched off until a hang seen in its first GPU runs is explained. */
 int vl_set_option(vl_ctx *ctx, int option, int value);
 int vl_get_option(vl_ctx *ctx, int option, int *value);
 
-/* Autotuner: times the candidate launch configurations (x+y per z-plane or
+/* Autotuner (launch shapes only; no passage of the paper defines it, and it
+ * never changes results beyond rounding): times the candidate launch configurations (x+y per z-plane or
  * separate sweeps, x lanes along the line or the split x solve and its lines
  * per wave, XCD tile order on or off, sources fused into the z sweep or
  * separate) on the bound buffers, a
@@ -288,7 +353,10 @@ int vl_get_option(vl_ctx *ctx, int option, int *value);
  * for the same shapes does no timing.  No-op for VL_F64. */
 int vl_tune(vl_ctx *ctx, const char *cache_path);
 
-/* Adjoint of n_steps steps (FP32 contexts; for VL_F64 both return VL_E_STATE).
+/* Adjoint of n_steps steps (FP32 contexts; for VL_F64 both return VL_E_STATE):
+ * the transpose of the step of vl_step, for fitting the parameters of
+ * Eq. (1) (D, lambda per substrate; S_i, U_i per cell) to observed fields, the
+ * calibration use that section "Introduction and Motivation" motivates.
  * For a scalar loss L whose gradient with respect to the field after n_steps
  * steps is grad_final (device, field layout, field_elems floats), computes
  *   grad_rho0 (device, field layout; may be NULL)  dL/d(field now),
@@ -310,7 +378,9 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace,
                const void *grad_final, void *grad_rho0, double *dD, double *dlambda,
                double *dS, double *dU);
 
-/* Per-kernel timing.  While enabled, vl_step launches without a graph and
+/* Per-kernel timing (the per-function profile of section "Profiling;
+ * Identifying Hot Spots", which found the diffusion solves to be about two
+ * thirds of the run time).  While enabled, vl_step launches without a graph and
  * brackets every kernel with HIP events on the bound stream; so does
  * vl_adjoint.
  * vl_kernel_stats synchronises and reports, for one VL_K_* kind, the number
