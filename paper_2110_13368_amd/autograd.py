@@ -16,18 +16,27 @@ import torch
 from .binding import Context
 
 
+def _host(a) -> np.ndarray:
+    """float64 host copy of a numpy array or torch tensor."""
+    if isinstance(a, torch.Tensor):
+        return a.detach().cpu().double().numpy()
+    return np.asarray(a, np.float64)
+
+
 def flat_params(ctx: Context):
     """Current D, lambda (float64, one per volume) and S, U (float64, per
-    simulation its cells x n_sub, concatenated) of a context."""
-    D = np.concatenate([np.asarray(s.D, np.float64).ravel() for s in ctx.sims])
-    lam = np.concatenate([np.asarray(s.lam, np.float64).ravel() for s in ctx.sims])
-    S = np.concatenate([np.asarray(s.cells.S, np.float64).ravel() for s in ctx.sims] + [np.zeros(0)])
-    U = np.concatenate([np.asarray(s.cells.U, np.float64).ravel() for s in ctx.sims] + [np.zeros(0)])
+    simulation its cells as last uploaded x n_sub, concatenated) of a context."""
+    D = np.concatenate([p[0].ravel() for p in ctx.params])
+    lam = np.concatenate([p[1].ravel() for p in ctx.params])
+    cells = [c for c in ctx.cells if c is not None and c.n > 0]
+    S = np.concatenate([_host(c.S).ravel() for c in cells] + [np.zeros(0)])
+    U = np.concatenate([_host(c.U).ravel() for c in cells] + [np.zeros(0)])
     return tuple(torch.from_numpy(a.copy()) for a in (D, lam, S, U))
 
 
 def _load(ctx: Context, D, lam, S, U) -> None:
-    """Make the context's parameters equal D, lam, S, U (host float64)."""
+    """Make the context's parameters equal D, lam, S, U (host float64).  The
+    cells keep the positions, volumes and targets of their last upload."""
     state = getattr(ctx, "_autograd_params", None)
     if state is None:
         state = ctx._autograd_params = tuple(t.numpy().copy() for t in flat_params(ctx))
@@ -35,15 +44,23 @@ def _load(ctx: Context, D, lam, S, U) -> None:
     lam = lam.detach().cpu().double().numpy()
     S = S.detach().cpu().double().numpy()
     U = U.detach().cpu().double().numpy()
+    if S.size != state[2].size or U.size != state[3].size or D.size != state[0].size:
+        raise ValueError("parameter sizes do not match the context's current cells "
+                         "(call flat_params again after moving or re-uploading cells)")
     v = c = 0
     for k, s in enumerate(ctx.sims):
-        nv, nc = s.n_sub, s.cells.n * s.n_sub
+        nv, nc = s.n_sub, ctx.n_cells(k) * s.n_sub
         if not (np.array_equal(D[v:v + nv], state[0][v:v + nv]) and np.array_equal(lam[v:v + nv], state[1][v:v + nv])):
             ctx.update_substrates(k, D[v:v + nv], lam[v:v + nv])
         if nc and not (np.array_equal(S[c:c + nc], state[2][c:c + nc]) and np.array_equal(U[c:c + nc], state[3][c:c + nc])):
-            cl = s.cells
-            ctx.upload_cells(k, type(cl)(cl.pos, cl.V, S[c:c + nc].reshape(-1, s.n_sub),
-                                        U[c:c + nc].reshape(-1, s.n_sub), cl.rho_star))
+            cl = ctx.cells[k]
+            Sk, Uk = S[c:c + nc].reshape(-1, s.n_sub), U[c:c + nc].reshape(-1, s.n_sub)
+            if isinstance(cl.V, torch.Tensor):  # a device upload: keep its positions on the device
+                dev = cl.V.device
+                ctx.upload_cells_device(k, cl.pos, cl.V, torch.from_numpy(Sk).to(dev),
+                                        torch.from_numpy(Uk).to(dev), cl.rho_star)
+            else:
+                ctx.upload_cells(k, type(cl)(cl.pos, cl.V, Sk, Uk, cl.rho_star))
         v += nv
         c += nc
     ctx._autograd_params = (D.copy(), lam.copy(), S.copy(), U.copy())

@@ -292,10 +292,28 @@ def vl_kernel_stats(ctx, kind: int):
 
 # ---------------------------------------------------------------------------
 
+class DeviceCells:
+    """Cell arrays of a device upload (torch float64 tensors on the context's
+    device, kept by reference): pos (n, 3), V (n,), S / U / rho_star
+    (n, n_sub)."""
+
+    def __init__(self, pos, V, S, U, rho_star):
+        self.pos, self.V, self.S, self.U, self.rho_star = pos, V, S, U, rho_star
+
+    @property
+    def n(self) -> int:
+        return int(self.V.numel())
+
+
 class Context:
     """Owns a library context for a list of simulations (workload ``SimSpec``
     objects or anything with the same attributes), with its field and workspace
-    allocated as torch tensors on ``device`` and a torch stream of its own."""
+    allocated as torch tensors on ``device`` and a torch stream of its own.
+
+    ``cells[k]`` is simulation k's cell set as last uploaded through this
+    object (the spec's at construction, then whatever ``upload_cells`` or
+    ``upload_cells_device`` was given): the adjoint lays out its per-cell
+    gradients by these counts, and autograd re-uploads these positions."""
 
     def __init__(self, sims: Sequence, dt: Optional[float] = None, precision: int = VL_F32,
                  decay_split: int = VL_DECAY_ONCE, device: str = "cuda:0", set_initial: bool = True,
@@ -309,6 +327,9 @@ class Context:
         self.device = torch.device(device)
         self.dt = float(dt if dt is not None else self.sims[0].dt)
         self.h = vl_create(len(self.sims), precision, decay_split)
+        self.cells = [s.cells if getattr(s, "cells", None) is not None else None for s in self.sims]
+        # per simulation its current (D, lambda): the spec's, then whatever update_substrates set
+        self.params = [(np.asarray(s.D, np.float64).copy(), np.asarray(s.lam, np.float64).copy()) for s in self.sims]
         try:
             for k, s in enumerate(self.sims):
                 vl_set_grid(self.h, k, *s.shape, *s.h, *s.lo)
@@ -336,6 +357,8 @@ class Context:
             if upload_cells:
                 self.n_out = [self.upload_cells(k, s.cells) if s.cells.n > 0 else 0
                               for k, s in enumerate(self.sims)]
+            else:
+                self.cells = [None] * len(self.sims)
         except Exception:
             vl_destroy(self.h)
             self.h = None
@@ -402,10 +425,19 @@ class Context:
 
     def update_substrates(self, k: int, D, lam) -> None:
         vl_update_substrates(self.h, k, D, lam)
+        self.params[k] = (np.asarray(D, np.float64).copy(), np.asarray(lam, np.float64).copy())
+
+    def n_cells(self, k: int) -> int:
+        """Cells of simulation k as last uploaded through this object."""
+        c = self.cells[k]
+        return 0 if c is None else int(c.n)
 
     def upload_cells(self, k: int, cells) -> int:
-        return vl_upload_cells(self.h, k, cells.pos, cells.V, cells.S, cells.U, cells.rho_star,
-                               self.sims[k].n_sub)
+        n_out = vl_upload_cells(self.h, k, cells.pos, cells.V, cells.S, cells.U, cells.rho_star,
+                                self.sims[k].n_sub)
+        self.cells[k] = cells
+        self._autograd_params = None
+        return n_out
 
     def upload_cells_device(self, k: int, pos, V, S, U, rho_star) -> int:
         """Cells from torch tensors on this context's device (float64: pos
@@ -421,7 +453,10 @@ class Context:
             raise ValueError("cell tensor shapes do not match")
         if self.stream is not None:  # the tensors were written on the caller's stream
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        return vl_upload_cells_dev(self.h, k, n, *[t.data_ptr() for t in ts])
+        n_out = vl_upload_cells_dev(self.h, k, n, *[t.data_ptr() for t in ts])
+        self.cells[k] = DeviceCells(*ts)
+        self._autograd_params = None
+        return n_out
 
     # -- stepping and diagnostics --
     def step(self, n: int = 1) -> None:
@@ -473,7 +508,7 @@ class Context:
         if g.numel() != self.field_elems:
             raise ValueError(f"grad_final must hold {self.field_elems} elements")
         g0 = torch.zeros_like(g)
-        total = sum(s.cells.n * s.n_sub for s in self.sims)
+        total = sum(self.n_cells(k) * s.n_sub for k, s in enumerate(self.sims))
         dS = torch.zeros(max(total, 1), dtype=torch.float64, device=self.device)
         dU = torch.zeros(max(total, 1), dtype=torch.float64, device=self.device)
         torch.cuda.synchronize(self.device)
@@ -490,10 +525,11 @@ class Context:
         g0, dD, dl, dS, dU = self.adjoint_flat(n_steps, ckpt_every, self.to_field_layout(grad_final))
         out, v, c = [], 0, 0
         for k, s in enumerate(self.sims):
-            nc = s.cells.n * s.n_sub
+            n = self.n_cells(k)
+            nc = n * s.n_sub
             out.append({"rho0": self.from_field_layout(g0, k).clone(), "D": dD[v:v + s.n_sub].numpy(),
                         "lambda": dl[v:v + s.n_sub].numpy(),
-                        "S": dS[c:c + nc].reshape(s.cells.n, s.n_sub), "U": dU[c:c + nc].reshape(s.cells.n, s.n_sub)})
+                        "S": dS[c:c + nc].reshape(n, s.n_sub), "U": dU[c:c + nc].reshape(n, s.n_sub)})
             v += s.n_sub
             c += nc
         return out
