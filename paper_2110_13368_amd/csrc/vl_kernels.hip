@@ -437,10 +437,15 @@ hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
 }
 
 // Per occupied voxel and substrate, walk its cells in upload order (FP64):
-//   a_i = k_i S_i rho*_i,  b_i = 1 + k_i (S_i + U_i),  k_i = dt V_i / V_vox,
-//   composite: A <- A + a_i B,  B <- B b_i  so that applying the cells one
-//   after another equals rho <- (rho + A) / B.
-// FP32 path: (A, 1/B); FP64 path: the per-cell (a_i, b_i) in sorted order.
+//   a_i = k_i S_i rho*_i,  b_i = 1 + k_i (S_i + U_i),  k_i = dt V_i / V_vox.
+// Applying the cells one after another maps rho to rho R + P with
+//   R <- R / b_i,  P <- (P + a_i) / b_i  (from R = 1, P = 0),
+// i.e. R = 1/B and P = A/B of the composite (rho + A)/B, A = sum a_i prod_{j<i}
+// b_j, B = prod b_i.  Both stay bounded whatever the number of cells:
+// 0 < R <= 1 and P lies between 0 and the largest rho*_i, where A and B
+// themselves grow without bound (B passes the FP32 range after about 150
+// fast cells).  FP32 path: (P, R), applied as fmaf(rho, R, P); FP64 path: the
+// per-cell (a_i, b_i) in sorted order.
 __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
                                   const int *__restrict__ seg_start, int n_occ, int ns,
                                   const double *__restrict__ V, const double *__restrict__ S,
@@ -454,7 +459,7 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
     if (g >= (long long)n_occ * ns) return;
     const int seg = (int)(g / ns), s = (int)(g % ns);
     const int out = pos ? pos[seg] : seg;
-    double A = 0.0, B = 1.0;
+    double P = 0.0, R = 1.0;
     for (int p = seg_start[seg]; p < seg_start[seg + 1]; ++p) {
         const int i = (int)(keys[p] & 0xFFFFFFull);
         const double k = dt * V[i] / vvox;
@@ -465,10 +470,10 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
         if (krs) krs[(size_t)p * ns + s] = k * RS[q];
         if (s == 0 && kcell) kcell[p] = k;
         if (s == 0 && cell_of) cell_of[p] = i;
-        A = A + a * B;
-        B = B * b;
+        P = (P + a) / b;
+        R = R / b;
     }
-    const float2 c32 = make_float2((float)A, (float)(1.0 / B));
+    const float2 c32 = make_float2((float)P, (float)R);
     if (comp32) comp32[(size_t)out * ns + s] = c32;
     if (comp32_v) comp32_v[(size_t)s * v_stride + seg] = c32;  // substrate-major
 }
@@ -531,7 +536,8 @@ __device__ __forceinline__ int find_slot_i(const int *__restrict__ prefix, int c
 }
 
 // The composite of occupied voxel jl (of simulation C) on substrate s:
-// rho <- (rho + A) * (1/B).
+// rho <- rho R + P, one fused multiply-add (the same operation wherever the
+// sources are applied, so every placement gives the same bits).
 __device__ __forceinline__ void apply_composite(const SimCells &C, int jl, int s, const SubDev *__restrict__ subs,
                                                 const int *__restrict__ occ_vox, const float2 *__restrict__ comp,
                                                 float *__restrict__ field)
@@ -539,7 +545,7 @@ __device__ __forceinline__ void apply_composite(const SimCells &C, int jl, int s
     const int v = occ_vox[C.occ_base + jl];
     const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
     float *p = field + subs[C.sub0 + s].base + v;
-    *p = (*p + ab.x) * ab.y;
+    *p = fmaf(*p, ab.y, ab.x);
 }
 
 // FP32: one thread per (occupied voxel, substrate).

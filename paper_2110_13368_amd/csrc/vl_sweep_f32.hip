@@ -323,7 +323,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
                         const float2 ab = src.comp[C.comp_base + (size_t)e * C.ns + S.sub];
                         const unsigned off = (unsigned)vox * 4u;
                         const float r = bload(rv, off, 0);
-                        bstore(rv, off, 0, (r + ab.x) * ab.y);
+                        bstore(rv, off, 0, fmaf(r, ab.y, ab.x));
                     }
                 }
             }

@@ -299,7 +299,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     };
     // cell sources of the previous step carried into this solve (uniform):
     // each x-line's range [e0, e1) of the voxel-ordered occupied voxels, the
-    // voxels, and their FP32 composites (A, 1/B) of this substrate (one
+    // voxels, and their FP32 composites (P, R) of this substrate (one
     // contiguous run per substrate)
     const SimCells *CC = CARRY ? &carry.cells[S.sim] : nullptr;
     const bool carried = CC != nullptr && CC->xs_base >= 0;
@@ -323,7 +323,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
         const vl_u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(ab_r, (int)(ok ? (unsigned)e * 8u : kOff), 0, 0);
         ab = make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
     };
-    // rho <- (rho + A) * (1/B) on the occupied voxels of the chunk: each
+    // rho <- rho R + P on the occupied voxels of the chunk: each
     // entry's lane writes its composite to the wave's LDS slot of that voxel
     // and marks the voxel in its owner lane's mask; owners then update their
     // registers.  Lanes talk through LDS here: the wavefront-scope fences keep
@@ -343,7 +343,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
         for (int t = 0; t < K; ++t)
             if (mk & (1u << t)) {
                 const float2 q = cs_ab[wave][K * lane + t];
-                r[t] = (r[t] + q.x) * q.y;
+                r[t] = fmaf(r[t], q.y, q.x);
             }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     };

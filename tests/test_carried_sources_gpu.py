@@ -119,3 +119,37 @@ def test_carried_sources_option_values():
             ctx.set_option(vb.VL_OPT_FUSE_SOURCES, 3)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("x_lanes", [0, 1])
+def test_hundreds_of_fast_cells_in_one_voxel(x_lanes):
+    """300 cells at the largest rates of the configurations (S = U = 10 /min,
+    V = 4000 um^3 in 10 um voxels, so every cell divides by b = 1.8) in one
+    voxel and 200 in another: the composite of a voxel is (prod b)^-1 ~ 1e-77,
+    far outside FP32, yet every placement must give the sequential update's
+    field (bitwise equal to each other, within 1e-5 of the oracle)."""
+    rng = np.random.default_rng(W.SEED_BASE + 950)
+    spec = W.make_sim(rng, (140, 9, 7), (10.0, 10.0, 10.0), 2, dtype="f32", bc="mixed", n_cells=50)
+    centre = lambda i, j, k: [spec.lo[0] + (i + 0.5) * 10.0, spec.lo[1] + (j + 0.5) * 10.0,
+                              spec.lo[2] + (k + 0.5) * 10.0]
+    hot = np.array([centre(70, 4, 3)] * 300 + [centre(3, 1, 5)] * 200)
+    pos = np.concatenate([hot, spec.cells.pos])
+    n = pos.shape[0]
+    S = np.concatenate([np.full((500, 2), 10.0), spec.cells.S])
+    U = np.concatenate([np.full((500, 2), 10.0), spec.cells.U])
+    V = np.concatenate([np.full(500, 4000.0), spec.cells.V])
+    rs = np.concatenate([rng.uniform(0.0, 40.0, (500, 2)), spec.cells.rho_star])
+    spec.cells = W.Cells(pos=pos, V=V, S=S, U=U, rho_star=rs)
+    assert n == 550
+    fields = {}
+    for mode in (0, 1, 2):
+        if mode == 2 and not x_lanes:
+            continue
+        (f,), n_out = run_gpu([spec], 6, x_lanes=x_lanes, sources_mode=mode)
+        assert n_out == [0]
+        assert np.all(np.isfinite(f))
+        fields[mode] = f
+    ref = fields[0]
+    for mode, f in fields.items():
+        assert np.array_equal(f, ref), mode
+    assert_close(ref, run_oracle(spec, 6), 1e-5, "500 fast cells in two voxels")
