@@ -41,10 +41,19 @@ def _oracle_grads(spec, target, mode, n_steps):
 
 
 def _gpu_grads(specs, finals, mode, n_steps, ckpt, x_lanes=0):
+    """GPU gradients; x_lanes None tunes the launch configuration first, as the
+    benchmark does (tuning overwrites the field, which is then set again)."""
     decay = vb.VL_DECAY_ONCE if mode == O.DECAY_ONCE else vb.VL_DECAY_THIRDS
     ctx = vb.Context(specs, decay_split=decay, device="cuda:0")
     try:
-        ctx.set_option(vb.VL_OPT_X_LANES, x_lanes)
+        if x_lanes is None:
+            ctx.tune(None)
+            for k, s in enumerate(specs):
+                ctx.set_field(k, s.rho0)
+            print(f"tuned: x lanes {ctx.get_option(vb.VL_OPT_X_LANES)}, "
+                  f"lines per wave {ctx.get_option(vb.VL_OPT_X_LANE_LINES)}", flush=True)
+        else:
+            ctx.set_option(vb.VL_OPT_X_LANES, x_lanes)
         before = [ctx.get_field(k).copy() for k in range(len(specs))]
         g = ctx.adjoint(n_steps, ckpt, [f.astype(np.float32) for f in finals])
         out = [{k: (v.double().cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)) for k, v in d.items()}
@@ -280,5 +289,160 @@ def test_autograd_function_and_parameter_update():
         _close(lam2.grad.numpy(), o["lambda"], "autograd dlambda")
         _close(S2.grad.cpu().numpy().reshape(-1, spec.n_sub), o["S"], "autograd dS")
         _close(U2.grad.cpu().numpy().reshape(-1, spec.n_sub), o["U"], "autograd dU")
+    finally:
+        ctx.close()
+
+
+# --------------------------------------------------------------------------
+# The differentiation workload at its stated size: 100^3 x 2, 2e4 cells in a
+# Gaussian ball, 200 FP32 steps with a checkpoint every 20.  The loss is
+# L = 1/2 |rho_T - target|^2 with the target a forward run whose D, lambda, S
+# and U are multiplied by exp(0.1 N(0, 1)) (seeded).  Sixteen parameters: D and
+# lambda of both substrates and S or U of twelve seeded-random in-domain cells,
+# against FP64 central differences of the oracle with h = 1e-6 |p|.  The loss
+# is about 1e6, so L(p + h) - L(p - h) formed from two rounded losses would
+# lose the difference; it is formed from the fields instead, as
+#   1/2 sum (rho+ - rho-) (rho+ + rho- - 2 target),
+# which equals it exactly in real arithmetic.
+
+DIFF_STEPS, DIFF_CKPT, DIFF_H = 200, 20, 1e-6
+
+
+@pytest.fixture(scope="module")
+def differentiation_case():
+    wl = W.differentiation()
+    spec = wl.sims[0]
+    assert wl.steps == DIFF_STEPS and spec.shape == (100, 100, 100) and spec.cells.n == 20000
+    rng = np.random.default_rng(W.SEED_BASE + 4004)
+    pert = copy.deepcopy(spec)
+    pert.D = spec.D * np.exp(0.1 * rng.normal(size=spec.D.shape))
+    pert.lam = spec.lam * np.exp(0.1 * rng.normal(size=spec.lam.shape))
+    pert.cells.S = spec.cells.S * np.exp(0.1 * rng.normal(size=spec.cells.S.shape))
+    pert.cells.U = spec.cells.U * np.exp(0.1 * rng.normal(size=spec.cells.U.shape))
+    tsim = O.from_spec(pert)
+    tsim.step(DIFF_STEPS)
+    target = tsim.get_field()
+    tsim.close()
+    o, r = _oracle_grads(spec, target, O.DECAY_ONCE, DIFF_STEPS)
+    g = _gpu_grads([spec], [r], O.DECAY_ONCE, DIFF_STEPS, ckpt=DIFF_CKPT, x_lanes=None)[0]
+    vox = O.from_spec(spec).cell_voxels()
+    inside = np.flatnonzero(vox >= 0)
+    cells = rng.choice(inside, size=12, replace=False)
+    params = [("D", s) for s in range(2)] + [("lam", s) for s in range(2)]
+    params += [("S" if j % 2 == 0 else "U", (int(i), int(rng.integers(0, 2)))) for j, i in enumerate(cells)]
+    return spec, target, o, g, params
+
+
+def _field_after(spec, name, idx, value):
+    sp = copy.deepcopy(spec)
+    arr = (sp.cells.S if name == "S" else sp.cells.U if name == "U" else sp.D if name == "D" else sp.lam).copy()
+    arr[idx] = value
+    if name in ("S", "U"):
+        setattr(sp.cells, name, arr)
+    else:
+        setattr(sp, name, arr)
+    sim = O.from_spec(sp)
+    sim.step(DIFF_STEPS)
+    f = sim.get_field()
+    sim.close()
+    return f
+
+
+def _central(spec, target, name, idx):
+    base = {"S": spec.cells.S, "U": spec.cells.U, "D": spec.D, "lam": spec.lam}[name]
+    p = float(base[idx])
+    h = DIFF_H * abs(p)
+    fp = _field_after(spec, name, idx, p + h)
+    fm = _field_after(spec, name, idx, p - h)
+    return 0.5 * float(np.sum((fp - fm) * (fp + fm - 2.0 * target))) / (2.0 * h)
+
+
+def test_differentiation_workload_gpu_adjoint_matches_oracle_adjoint(differentiation_case):
+    spec, _, o, g, _ = differentiation_case
+    _compare(g, o, "100^3x2, 200 steps, checkpoints every 20")
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_differentiation_workload_sixteen_parameters_vs_fd(differentiation_case, part):
+    spec, target, o, g, params = differentiation_case
+    assert len(params) == 16
+    key = {"D": "D", "lam": "lambda", "S": "S", "U": "U"}
+    for name, idx in params[4 * part:4 * part + 4]:
+        fd = _central(spec, target, name, idx)
+        got = float(g[key[name]][idx])
+        orc = float(o[key[name]][idx])
+        print(f"{name}{idx}: gpu {got:.8e}  oracle adjoint {orc:.8e}  fd(h=1e-6|p|) {fd:.8e}  "
+              f"rel gpu {abs(got - fd) / abs(fd):.2e}  rel oracle {abs(orc - fd) / abs(fd):.2e}", flush=True)
+        # the oracle's adjoint is the exact FP64 transpose: the difference to
+        # the central difference is its truncation and rounding
+        assert abs(orc - fd) <= 1e-5 * abs(fd), (name, idx, orc, fd)
+        assert abs(got - fd) <= TOL * abs(fd), (name, idx, got, fd)
+
+
+def _fewer_cells(cells, n):
+    c = copy.deepcopy(cells)
+    c.pos, c.V, c.S, c.U, c.rho_star = c.pos[:n], c.V[:n], c.S[:n], c.U[:n], c.rho_star[:n]
+    return c
+
+
+def test_adjoint_after_reupload_with_fewer_cells():
+    """Per-cell gradients are laid out by the cells uploaded now: in a batch of
+    two, simulation 0 is re-uploaded with fewer cells; both simulations' dS and
+    dU (and the rest) must match the oracle's adjoint for the cells in place."""
+    s0, t0 = _case(1201, (18, 14, 11), n_cells=40)
+    s1, t1 = _case(1202, (15, 16, 12), n_cells=30)
+    n_steps = 5
+    ctx = vb.Context([s0, s1], device="cuda:0")
+    try:
+        fewer = _fewer_cells(s0.cells, 17)
+        ctx.upload_cells(0, fewer)
+        assert ctx.n_cells(0) == 17 and ctx.n_cells(1) == 30
+        s0b = copy.copy(s0)
+        s0b.cells = fewer
+        o0, r0 = _oracle_grads(s0b, t0, O.DECAY_ONCE, n_steps)
+        o1, r1 = _oracle_grads(s1, t1, O.DECAY_ONCE, n_steps)
+        g = ctx.adjoint(n_steps, 2, [r0.astype(np.float32), r1.astype(np.float32)])
+        g = [{k: (v.double().cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)) for k, v in d.items()} for d in g]
+        assert g[0]["S"].shape == (17, 2) and g[1]["S"].shape == (30, 2)
+        _compare(g[0], o0, "re-uploaded sim 0")
+        _compare(g[1], o1, "sim 1 after sim 0's re-upload")
+    finally:
+        ctx.close()
+
+
+def test_autograd_keeps_cells_moved_on_the_device():
+    """After a device upload of moved cells, autograd's forward pass with new
+    S, U re-uploads the moved positions, not the spec's original ones."""
+    import torch
+
+    from paper_2110_13368_amd.autograd import LODStepFn, flat_params
+
+    spec, target = _case(1301, (16, 12, 10), bc="mixed", n_cells=25)
+    n_steps = 4
+    ctx = vb.Context([spec], device="cuda:0")
+    try:
+        moved = copy.deepcopy(spec.cells)
+        moved.pos = moved.pos + np.array([spec.h[0], -0.5 * spec.h[1], 0.0])
+        moved.pos[:, 0] = np.minimum(moved.pos[:, 0], spec.lo[0] + spec.shape[0] * spec.h[0] - 1.0)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+        ctx.upload_cells_device(0, dev(moved.pos), dev(moved.V), dev(moved.S), dev(moved.U), dev(moved.rho_star))
+        D, lam, S, U = flat_params(ctx)
+        S2, U2 = (S * 1.2).requires_grad_(), (U * 0.8).requires_grad_()
+        rho0 = ctx.to_field_layout([spec.rho0]).requires_grad_()
+        out = LODStepFn.apply(rho0, D, lam, S2, U2, ctx, n_steps, 2)
+        sp = copy.deepcopy(spec)
+        sp.cells = moved
+        sp.cells.S = S2.detach().numpy().reshape(-1, spec.n_sub)
+        sp.cells.U = U2.detach().numpy().reshape(-1, spec.n_sub)
+        fwd = O.from_spec(sp)
+        fwd.step(n_steps)
+        _close(ctx.from_field_layout(out, 0).detach().double().cpu().numpy(), fwd.get_field(),
+               "forward with moved cells and new rates", 1e-5)
+        loss = 0.5 * ((ctx.from_field_layout(out, 0) - torch.as_tensor(target, dtype=torch.float32,
+                                                                       device="cuda:0")) ** 2).sum()
+        loss.backward()
+        o, _ = _oracle_grads(sp, target, O.DECAY_ONCE, n_steps)
+        _close(S2.grad.cpu().numpy().reshape(-1, spec.n_sub), o["S"], "dS with moved cells")
+        _close(U2.grad.cpu().numpy().reshape(-1, spec.n_sub), o["U"], "dU with moved cells")
     finally:
         ctx.close()

@@ -410,37 +410,6 @@ def test_device_field_io_and_aos():
 
 
 # --------------------------------------------------------------------------
-# full-size configurations, in the launch shape the benchmark times, checked
-# on sampled substrates (substrates are independent) or sampled simulations
-
-def test_full_single_large_sampled():
-    wl = W.single_large()
-    spec = wl.sims[0]
-    (got,), _ = run_gpu([spec], 3)
-    for s in (0, 3):
-        want = run_oracle(subset(spec, [s]), 3)
-        assert_close(got[s:s + 1], want, 1e-5, f"200^3 substrate {s}")
-
-
-def test_full_tumour_scale_sampled():
-    wl = W.tumour_scale()
-    spec = wl.sims[0]
-    (got,), _ = run_gpu([spec], 2)
-    s = int(np.argmax(spec.D))  # the widest stencil coupling
-    want = run_oracle(subset(spec, [s]), 2)
-    assert_close(got[s:s + 1], want, 1e-5, f"400^3 substrate {s}")
-
-
-def test_full_batched_sampled():
-    wl = W.batched()
-    fields, n_out = run_gpu(wl.sims, 3)
-    assert sum(n_out) == 0
-    sizes = [int(np.prod(s.shape)) for s in wl.sims]
-    for k in (int(np.argmin(sizes)), int(np.argmax(sizes)), 17):
-        assert_close(fields[k], run_oracle(wl.sims[k], 3), 1e-5, f"batch sim {k} {wl.sims[k].shape}")
-
-
-# --------------------------------------------------------------------------
 # x and y of one z-plane per workgroup (planes that fit in LDS) against the
 # separate x and y sweeps: the same operations, so bitwise the same field.
 
