@@ -18,8 +18,13 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# VOXLOD_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; run the tests with libasan
+# preloaded, see run_sanitized_tests.py)
+SANITIZE = os.environ.get("VOXLOD_ORACLE_SANITIZE", "") == "1"
+LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 SOURCES = [os.path.join(_HERE, "oracle.c")]
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 
 NEUMANN, DIRICHLET = 0, 1
 DECAY_ONCE, DECAY_THIRDS = 0, 1
@@ -35,6 +40,8 @@ def build(force: bool = True) -> str:
         return LIB_PATH
     cmd = ["gcc", "-std=c11", "-O3", "-march=x86-64-v2", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp"] + SOURCES + ["-lm"]
+    if SANITIZE:
+        cmd[1:1] = SANITIZE_FLAGS
     subprocess.run(cmd, check=True)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
     return LIB_PATH
