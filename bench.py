@@ -184,23 +184,39 @@ def kernel_profile(ctx, steps: int):
 
 
 def copy_reference(nbytes: int, reps: int = 20):
-    """Device-to-device copy of nbytes with a plain elementwise kernel: the
-    practical bandwidth ceiling, and the kernel of known traffic (nbytes read,
-    nbytes written per launch) that scales the FETCH_SIZE / WRITE_SIZE
-    counters."""
+    """Device-to-device copies of nbytes: torch's elementwise copy and the
+    library's copy probe (vl_copy_probe) with 4- and 16-byte accesses per
+    lane, ordinary or non-temporal loads and stores.  The fastest is the
+    practical bandwidth ceiling for a sweep (which reads and writes every
+    element once); each is a kernel of known traffic (nbytes read, nbytes
+    written per launch) that scales the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
+    from paper_2110_13368_amd import binding as vb
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / reps
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def rate(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return round(2 * nbytes / ((time.perf_counter() - t0) / reps) / 1e9, 1)
+
+    out = {"bytes": nbytes, "GBps_read_plus_write": rate(lambda: dst.copy_(src))}
+    probe = {}
+    for width in (4, 16):
+        for nt in (0, 3):
+            probe[f"width{width}_nt{nt}"] = rate(
+                lambda: vb.vl_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, width, nt, stream))
+    if not torch.equal(dst, src):
+        raise RuntimeError("vl_copy_probe: destination differs from source")
+    out["vl_copy_probe_GBps"] = probe
     del src, dst
     torch.cuda.empty_cache()
-    return {"bytes": nbytes, "GBps_read_plus_write": round(2 * nbytes / t / 1e9, 1)}
+    return out
 
 
 def cpu_baseline(wl, budget_s: float):

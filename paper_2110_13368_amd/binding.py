@@ -70,6 +70,7 @@ SIGNATURES = {
     "vl_adjoint": (_i, [_vp, _i, _i, _vp, _vp, _vp, _dp, _dp, _vp, _vp]),
     "vl_set_profiling": (_i, [_vp, _i]),
     "vl_kernel_stats": (_i, [_vp, _i, C.POINTER(C.c_longlong), _dp]),
+    "vl_copy_probe": (_i, [_vp, _vp, _sz, _i, _i, _vp]),
 }
 
 _lib = None
@@ -288,6 +289,12 @@ def vl_kernel_stats(ctx, kind: int):
     n, ms = C.c_longlong(0), C.c_double(0)
     _check(lib().vl_kernel_stats(ctx, int(kind), C.byref(n), C.byref(ms)), "vl_kernel_stats")
     return int(n.value), float(ms.value)
+
+
+def vl_copy_probe(dst_ptr: int, src_ptr: int, nbytes: int, width: int = 16, nontemporal: int = 0,
+                  stream_ptr: int = 0) -> None:
+    _check(lib().vl_copy_probe(dst_ptr, src_ptr, nbytes, int(width), int(nontemporal), stream_ptr),
+           "vl_copy_probe")
 
 
 # ---------------------------------------------------------------------------

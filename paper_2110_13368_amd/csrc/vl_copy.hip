@@ -1,0 +1,73 @@
+// vl_copy.hip -- a plain device copy, the practical bandwidth ceiling that
+// the sweeps are measured against.  Each sweep reads and writes every element
+// once, so a copy of the same bytes is the fastest a sweep can be on this
+// memory system; the variants here (4-, 8- or 16-byte accesses per lane,
+// ordinary or non-temporal loads and stores) show which access shapes reach
+// it.  Also the kernel of known traffic (bytes read = bytes written = size)
+// that scales the HBM byte counters.
+#include "vl_internal.h"
+
+namespace vl {
+
+namespace {
+
+typedef unsigned cp_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned cp_u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCopyThreads = 256;
+constexpr int kCopyUnroll = 4;  // accesses in flight per thread
+
+template <typename T, bool NTL, bool NTS>
+__global__ void __launch_bounds__(kCopyThreads)
+copy_probe_kernel(const T *__restrict__ src, T *__restrict__ dst, size_t n)
+{
+    const size_t base = (size_t)blockIdx.x * (kCopyThreads * kCopyUnroll) + threadIdx.x;
+    T r[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + (size_t)u * kCopyThreads;
+        if (i < n) r[u] = NTL ? __builtin_nontemporal_load(src + i) : src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + (size_t)u * kCopyThreads;
+        if (i < n) {
+            if (NTS)
+                __builtin_nontemporal_store(r[u], dst + i);
+            else
+                dst[i] = r[u];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_typed(const void *src, void *dst, size_t bytes, int nt, hipStream_t st)
+{
+    const size_t n = bytes / sizeof(T);
+    const size_t per = (size_t)kCopyThreads * kCopyUnroll;
+    const dim3 grid((unsigned)((n + per - 1) / per)), block(kCopyThreads);
+    const T *s = (const T *)src;
+    T *d = (T *)dst;
+    switch (nt & 3) {
+    case 0: hipLaunchKernelGGL((copy_probe_kernel<T, false, false>), grid, block, 0, st, s, d, n); break;
+    case 1: hipLaunchKernelGGL((copy_probe_kernel<T, true, false>), grid, block, 0, st, s, d, n); break;
+    case 2: hipLaunchKernelGGL((copy_probe_kernel<T, false, true>), grid, block, 0, st, s, d, n); break;
+    default: hipLaunchKernelGGL((copy_probe_kernel<T, true, true>), grid, block, 0, st, s, d, n); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// width: bytes per lane access (4, 8 or 16); nt: bit 0 non-temporal loads,
+// bit 1 non-temporal stores.  bytes is a multiple of 16 and below 2^32 *
+// (kCopyThreads * kCopyUnroll) * width (checked by the caller).
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, int width, int nt, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    if (width == 4) return launch_typed<unsigned>(src, dst, bytes, nt, st);
+    if (width == 8) return launch_typed<cp_u32x2>(src, dst, bytes, nt, st);
+    return launch_typed<cp_u32x4>(src, dst, bytes, nt, st);
+}
+
+}  // namespace vl

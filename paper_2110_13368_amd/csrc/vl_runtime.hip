@@ -26,6 +26,8 @@ hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *
 // the adjoint's reverse x solve with the lanes along the line (vl_adjoint_xl.hip)
 hipError_t launch_adjoint_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *w,
                              const float *raw, double *part, hipStream_t st);
+// the ABI's copy probe (vl_copy.hip)
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, int width, int nt, hipStream_t st);
 }  // namespace vl
 
 // x-lines per wave of the lanes-along-the-line solve when not tuned
@@ -1886,6 +1888,20 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
         if (dD) dD[q] = gd;
         if (dlambda) dlambda[q] = gl;
     }
+    return VL_OK;
+}
+
+int vl_copy_probe(void *dst, const void *src, size_t bytes, int width, int nontemporal, void *stream)
+{
+    if (!dst || !src) return fail(VL_E_ARG, "vl_copy_probe: null buffer");
+    if (width != 4 && width != 8 && width != 16) return fail(VL_E_ARG, "vl_copy_probe: width must be 4, 8 or 16");
+    if (nontemporal < 0 || nontemporal > 3) return fail(VL_E_ARG, "vl_copy_probe: nontemporal must be in [0, 3]");
+    if (bytes % 16 != 0) return fail(VL_E_ARG, "vl_copy_probe: bytes must be a multiple of 16");
+    if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return fail(VL_E_ARG, "vl_copy_probe: buffers must be 16-byte aligned");
+    if (bytes / (size_t)width / 1024u >= (1ull << 31)) return fail(VL_E_ARG, "vl_copy_probe: bytes too large");
+    const char *a = (const char *)src, *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes) return fail(VL_E_ARG, "vl_copy_probe: buffers overlap");
+    VL_HIP(vl::launch_copy_probe(src, dst, bytes, width, nontemporal, (hipStream_t)stream));
     return VL_OK;
 }
 

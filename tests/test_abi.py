@@ -149,3 +149,15 @@ def test_options_on_the_host():
 
 def test_destroy_null_is_ok():
     vb.vl_destroy(None)
+
+
+def test_copy_probe_rejects_bad_arguments_on_the_host():
+    # all of these fail before any device call
+    assert _code(vb.vl_copy_probe, 0, 256, 1024) == vb.VL_E_ARG  # null destination
+    assert _code(vb.vl_copy_probe, 4096, 0, 1024) == vb.VL_E_ARG  # null source
+    assert _code(vb.vl_copy_probe, 4096, 8192, 1024, 2) == vb.VL_E_ARG  # width
+    assert _code(vb.vl_copy_probe, 4096, 8192, 1024, 16, 4) == vb.VL_E_ARG  # non-temporal bits
+    assert _code(vb.vl_copy_probe, 4096, 8192, 1000) == vb.VL_E_ARG  # not a multiple of 16
+    assert _code(vb.vl_copy_probe, 4100, 8192, 1024) == vb.VL_E_ARG  # misaligned
+    assert _code(vb.vl_copy_probe, 4096, 4608, 1024) == vb.VL_E_ARG  # overlapping
+    assert "overlap" in vb.vl_last_error()
