@@ -400,6 +400,24 @@ int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms
  * VL_E_HIP if the launch fails. */
 int vl_copy_probe(void *dst, const void *src, size_t bytes, int width, int nontemporal, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the FP64 sums of
+ * vl_mass without a context or workspace.  out_dev[q] (device memory, n_vols
+ * doubles) receives the sum of the n_vox elements starting at element
+ * q*vol_stride of field_dev (device memory of the given precision, VL_F32 or
+ * VL_F64), for q < n_vols; with vl_field_offset and vl_volume_stride this is
+ * one simulation's per-substrate mass.  Same kernels and summation order as
+ * vl_mass, so the sums are bitwise equal.  Asynchronous on stream (NULL = the
+ * null stream); no allocation and no synchronisation.  The partial sums live
+ * in a static array of the library on each GPU (64 volumes x 256 doubles,
+ * 128 KiB, held until the process ends), shared by every call on that GPU:
+ * calls that overlap on one GPU race.  The caller owns field_dev and
+ * out_dev.  VL_E_SHAPE for more than 64 volumes; VL_E_ARG for a null or
+ * misaligned buffer, n_vox < 1, or vol_stride < n_vox with several volumes;
+ * VL_E_HIP if a launch fails. */
+int vl_mass_noalloc(const void *field_dev, int precision, long long n_vox, int n_vols,
+                    long long vol_stride, double *out_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

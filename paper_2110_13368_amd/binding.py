@@ -71,6 +71,7 @@ SIGNATURES = {
     "vl_set_profiling": (_i, [_vp, _i]),
     "vl_kernel_stats": (_i, [_vp, _i, C.POINTER(C.c_longlong), _dp]),
     "vl_copy_probe": (_i, [_vp, _vp, _sz, _i, _i, _vp]),
+    "vl_mass_noalloc": (_i, [_vp, _i, C.c_longlong, _i, C.c_longlong, _vp, _vp]),
 }
 
 _lib = None
@@ -289,6 +290,12 @@ def vl_kernel_stats(ctx, kind: int):
     n, ms = C.c_longlong(0), C.c_double(0)
     _check(lib().vl_kernel_stats(ctx, int(kind), C.byref(n), C.byref(ms)), "vl_kernel_stats")
     return int(n.value), float(ms.value)
+
+
+def vl_mass_noalloc(field_ptr: int, precision: int, n_vox: int, n_vols: int, vol_stride: int, out_ptr: int,
+                    stream_ptr: int = 0) -> None:
+    _check(lib().vl_mass_noalloc(field_ptr, int(precision), int(n_vox), int(n_vols), int(vol_stride), out_ptr,
+                                 stream_ptr), "vl_mass_noalloc")
 
 
 def vl_copy_probe(dst_ptr: int, src_ptr: int, nbytes: int, width: int = 16, nontemporal: int = 0,

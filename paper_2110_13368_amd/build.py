@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoxlod.so")
 SOURCES = ["vl_runtime.hip", "vl_kernels.hip", "vl_sweep_f32.hip", "vl_sweep_xy.hip", "vl_sweep_xl.hip", "vl_adjoint.hip",
-           "vl_adjoint_xl.hip", "vl_copy.hip"]
+           "vl_adjoint_xl.hip", "vl_copy.hip", "vl_noalloc.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -239,6 +239,12 @@ hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ
 constexpr int kMassBlocks = 256;
 hipError_t launch_mass(const void *field, int is_f64, long long base, long long vol,
                        double *partials, double *out, hipStream_t st);
+// The same sums for nvols volumes of vol elements, vol_stride apart from
+// field, into out_dev[0..nvols), with the partial sums in the library's static
+// per-device array (vl_noalloc.hip) instead of a workspace.
+constexpr int kNoallocMaxVolumes = 64;
+hipError_t mass_noalloc(const void *field, int is_f64, long long vol, long long vol_stride, int nvols,
+                        double *out_dev, hipStream_t st);
 hipError_t launch_count_nonfinite(const void *field, int is_f64, const SubDev *subs,
                                   int nsubs, unsigned long long *count, hipStream_t st);
 

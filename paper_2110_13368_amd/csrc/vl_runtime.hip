@@ -1905,4 +1905,24 @@ int vl_copy_probe(void *dst, const void *src, size_t bytes, int width, int nonte
     return VL_OK;
 }
 
+int vl_mass_noalloc(const void *field_dev, int precision, long long n_vox, int n_vols, long long vol_stride,
+                    double *out_dev, void *stream)
+{
+    if (!field_dev || !out_dev) return fail(VL_E_ARG, "vl_mass_noalloc: null buffer");
+    if (precision != VL_F32 && precision != VL_F64)
+        return fail(VL_E_ARG, "vl_mass_noalloc: precision must be VL_F32 or VL_F64");
+    if (n_vox < 1) return fail(VL_E_ARG, "vl_mass_noalloc: n_vox must be >= 1");
+    if (n_vols < 1) return fail(VL_E_ARG, "vl_mass_noalloc: n_vols must be >= 1");
+    if (n_vols > vl::kNoallocMaxVolumes)
+        return fail(VL_E_SHAPE, "vl_mass_noalloc: at most " + std::to_string(vl::kNoallocMaxVolumes) +
+                                    " volumes per call (the static partial-sum array's size)");
+    if (n_vols > 1 && vol_stride < n_vox) return fail(VL_E_ARG, "vl_mass_noalloc: vol_stride must be >= n_vox");
+    const size_t esize = precision == VL_F32 ? 4 : 8;
+    if (reinterpret_cast<uintptr_t>(field_dev) % esize || reinterpret_cast<uintptr_t>(out_dev) % 8)
+        return fail(VL_E_ARG, "vl_mass_noalloc: misaligned buffer");
+    VL_HIP(vl::mass_noalloc(field_dev, precision == VL_F64, n_vox, n_vols > 1 ? vol_stride : 0, n_vols, out_dev,
+                            (hipStream_t)stream));
+    return VL_OK;
+}
+
 }  // extern "C"

@@ -161,3 +161,17 @@ def test_copy_probe_rejects_bad_arguments_on_the_host():
     assert _code(vb.vl_copy_probe, 4100, 8192, 1024) == vb.VL_E_ARG  # misaligned
     assert _code(vb.vl_copy_probe, 4096, 4608, 1024) == vb.VL_E_ARG  # overlapping
     assert "overlap" in vb.vl_last_error()
+
+
+def test_mass_noalloc_rejects_bad_arguments_on_the_host():
+    # all of these fail before any device call
+    assert _code(vb.vl_mass_noalloc, 0, vb.VL_F32, 10, 1, 10, 4096) == vb.VL_E_ARG  # null field
+    assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F32, 10, 1, 10, 0) == vb.VL_E_ARG  # null output
+    assert _code(vb.vl_mass_noalloc, 4096, 5, 10, 1, 10, 4096) == vb.VL_E_ARG  # precision
+    assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F32, 0, 1, 10, 4096) == vb.VL_E_ARG  # no voxels
+    assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F32, 10, 0, 10, 4096) == vb.VL_E_ARG  # no volumes
+    assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F32, 10, 65, 10, 4096) == vb.VL_E_SHAPE  # past the array
+    assert "64 volumes" in vb.vl_last_error()
+    assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F32, 10, 2, 9, 4096) == vb.VL_E_ARG  # overlapping volumes
+    assert _code(vb.vl_mass_noalloc, 4098, vb.VL_F32, 10, 1, 10, 4096) == vb.VL_E_ARG  # misaligned field
+    assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F64, 10, 1, 10, 4100) == vb.VL_E_ARG  # misaligned output
