@@ -76,7 +76,7 @@ def plane_fits(nx: int, ny: int) -> bool:
     """Whether a z-plane of nx x ny is solved by the x+y plane kernel (its LDS
     need: both pivot tables, the exchange slots, rows padded to odd length)."""
     cbx, cby = nx - 1 - (nx - 1) // 2, ny - 1 - (ny - 1) // 2
-    return (cbx + cby) * 8 + 256 * 4 + ny * (nx | 1) * 4 <= LDS_PER_WORKGROUP
+    return (cbx + cby) * 16 + 256 * 8 + ny * (nx | 1) * 4 <= LDS_PER_WORKGROUP
 
 
 def make_workload(name: str):

@@ -305,7 +305,7 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * an L2), with 0 tiles follow the workgroup index. */
 #define VL_OPT_XCD_ORDER 5
 /* VL_OPT_FUSE_XY (FP32 path, default 0): 1 solves x and y of every z-plane
- * that fits in LDS (160 KiB: about 200 x 200 voxels) in one workgroup, which
+ * that fits in LDS (160 KiB: up to 199 x 199 voxels) in one workgroup, which
  * reads and writes the field once for both solves; volumes with larger
  * planes keep the separate x and y sweeps.  Fields are bitwise identical
  * either way.  One plane per workgroup leaves its load, solve and store

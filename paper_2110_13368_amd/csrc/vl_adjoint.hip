@@ -29,7 +29,7 @@ template <int AXIS, int CAP>
 __device__ __forceinline__ void adjoint_tile(const SubDev &S, int local, int tile,
                                              const float2 *__restrict__ coef, float *__restrict__ w,
                                              const float *__restrict__ raw, double *__restrict__ part,
-                                             TileLds<CAP, AXIS == 0> &sh)
+                                             TileLds<CAP, AXIS == 0, float2, float> &sh)
 {
     constexpr int kChunks = (CAP + 63) / 64;
     float(&xch)[2][kWave] = sh.xch;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(128)
 adjoint_sweep(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
               float *__restrict__ w, const float *__restrict__ raw, double *__restrict__ part)
 {
-    __shared__ TileLds<CAP, AXIS == 0> sh;
+    __shared__ TileLds<CAP, AXIS == 0, float2, float> sh;
     const int tile = blockIdx.x;
     const int slot = find_slot(L.tile_prefix, L.count, tile);
     const int local = tile - L.tile_prefix[slot];

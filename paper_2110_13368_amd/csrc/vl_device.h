@@ -119,13 +119,28 @@ __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned voff,
 
 // LDS of one tile.  The x sweep needs a 64x64 staging block per wave (rows
 // padded to 65 floats, or 16 blocks of 4 rows padded to 260 floats: the same
-// size); the others only the exchange slots and the pivot table.
-template <int CAP, bool XSTAGE>
+// size); the others only the exchange slots and the pivot table.  The
+// forward sweeps keep both in FP64 (their recurrences run in FP64), the
+// adjoint's reverse solves in FP32.
+template <int CAP, bool XSTAGE, typename PIV = double2, typename XCH = double, int SX = 65>
 struct TileLds {
-    float xch[2][kWave];
-    float2 piv[CAP];
-    __attribute__((aligned(16))) float stage[XSTAGE ? 2 * 64 * 65 : 1];
+    XCH xch[2][kWave];
+    PIV piv[CAP];
+    __attribute__((aligned(16))) float stage[XSTAGE ? 2 * 64 * SX : 1];
 };
+
+// Chunks of the forward split x sweep's stage: a wave holds at most CAP
+// columns of its 64 rows, so lines of up to 65 voxels (CAP 32) move 32
+// columns at a time through a 64 x 33 block per wave, half the LDS of the
+// 64 x 65 block the longer lines use (which lets twice as many workgroups
+// share a CU).
+template <int CAP>
+struct XStage {
+    static constexpr int W = CAP <= 32 ? 32 : 64;  // columns per chunk
+    static constexpr int SX = W + 1;                // row stride in floats (odd: no bank conflicts)
+};
+template <int CAP, bool XSTAGE>
+using FwdLds = TileLds<CAP, XSTAGE, double2, double, XStage<CAP>::SX>;
 
 // ---------------------------------------------------------------------------
 // x lines with 16-byte transfers (long lines, CAP >= 160).  A 64-row x

@@ -27,12 +27,12 @@ constexpr int kCaps[kNumCaps] = {32, 64, 96, 100, 128, 160, 200, 256};
 constexpr int kXYThreads = 512;
 constexpr size_t kXYMaxLds = 160 * 1024;
 __host__ __device__ constexpr int xy_row_stride(int nx) { return nx | 1; }
-// dynamic LDS of that kernel: pivot tables of both axes, one exchange slot
-// per lane of each wave pair, the plane
+// dynamic LDS of that kernel: pivot tables of both axes (FP64 pairs), one
+// FP64 exchange slot per lane of each wave pair, the plane
 inline size_t xy_lds_bytes(int nx, int ny)
 {
     const size_t cbx = (size_t)(nx - 1 - (nx - 1) / 2), cby = (size_t)(ny - 1 - (ny - 1) / 2);
-    return (cbx + cby) * 8 + (size_t)(kXYThreads / 2) * 4 + (size_t)ny * xy_row_stride(nx) * 4;
+    return (cbx + cby) * 16 + (size_t)(kXYThreads / 2) * 8 + (size_t)ny * xy_row_stride(nx) * 4;
 }
 
 // One (simulation, substrate) volume.
@@ -48,6 +48,7 @@ struct SubDev {
     float dval32[6];     // Dirichlet values (FP32 path)
     float mid32[3][2];   // per axis: (g1, g2) of the middle row of the split solve
     double dval64[6];    // Dirichlet values (FP64 path)
+    double mid64[3][2];  // per axis: (g1, g2) of the middle row, FP64 (FP32 path's recurrences)
     double c[3];         // dt*D/h_a^2 per axis
     double sigma;        // diagonal shift lambda*dt/3 (decay split over the solves) or 0
     double fdec;         // decay factor 1/(1 + lambda*dt) applied after the x solve, or 1
@@ -143,14 +144,16 @@ struct StepQueue {
 // Kernel launchers (defined in the .hip files, called by the runtime).
 
 // a1: coefficients.  One thread per (volume, axis), FP64 recurrences.
-hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32,
+// coefh receives the half-line table in FP64 (same indexing as coef32): the
+// forward FP32 sweeps run their recurrences in FP64 from it.
+hipError_t launch_coefficients(const SubDev *subs, int nsubs, float2 *coef32, double2 *coefh,
                                double2 *coef64, SubDev *subs_rw, hipStream_t st);
 
 // a3+a4 for volumes whose z-plane fits in LDS: x then y solve of one plane per
 // workgroup (tile_prefix counts planes); lds_bytes as from xy_lds_bytes.
 // prepare_sweep_xy raises the kernel's dynamic-LDS limit (once per device).
 hipError_t prepare_sweep_xy(size_t lds_bytes);
-hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev *subs, const float2 *coef,
+hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev *subs, const double2 *coef,
                            float *field, hipStream_t st);
 
 // a3 with lanes along the line: tables (one 64-thread workgroup per volume,
@@ -165,7 +168,7 @@ hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *s
 // raw (may be null, same layout as the field) receives each solve's output
 // before the Dirichlet projection, for the adjoint's replay.
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
-                            const SubDev *subs, const float2 *coef, float *field, float *raw,
+                            const SubDev *subs, const double2 *coef, float *field, float *raw,
                             const FusedSources &src, hipStream_t st);
 
 // a9: adjoint sweep along axis, in place on w (same layout as the field).  The
@@ -191,7 +194,7 @@ hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *o
 
 // a8: the whole step as one persistent launch of `grid` workgroups.
 hipError_t launch_step_persistent(int cap_idx, int grid, const StepQueue &Q, const SubDev *subs,
-                                  const float2 *coef, float *field, const FusedSources &src,
+                                  const double2 *coef, float *field, const FusedSources &src,
                                   hipStream_t st);
 hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks);
 

@@ -17,12 +17,14 @@ namespace vl {
 // b_in = 1 + 2c + sigma, and 1 + sigma for a one-voxel line.
 //  * full-line table (FP64 plain path): d_0 = b_0, d_i = b_i - c^2/d_{i-1};
 //    entries (1/d_i, c/d_i), i < n.
-//  * half-line table (FP32 split solve): pivots from one end, d_0 = b_end,
-//    d_t = b_in - c^2/d_{t-1}, t < cb = n - 1 - m with m = (n-1)/2; entries
-//    (f/d_t, c/d_t) where f is the decay factor folded into the x solve.
+//  * half-line table (split solve of the FP32 path): pivots from one end,
+//    d_0 = b_end, d_t = b_in - c^2/d_{t-1}, t < cb = n - 1 - m with
+//    m = (n-1)/2; entries (f/d_t, c/d_t) where f is the decay factor folded
+//    into the x solve.  Stored twice: in FP64 for the forward sweeps, whose
+//    recurrences run in FP64, and in FP32 for the adjoint's reverse solves.
 //    Middle row m: gamma = b_m - c^2/d_{m-1} [m>0] - c^2/d_{cb-1} [cb>0],
 //    x_m = r_m f/gamma + (c/gamma) (y_{m-1} + z_{m+1}).
-__global__ void coefficients_kernel(SubDev *subs, int nsubs, float2 *coef32, double2 *coef64)
+__global__ void coefficients_kernel(SubDev *subs, int nsubs, float2 *coef32, double2 *coefh, double2 *coef64)
 {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nsubs * 3) return;
@@ -45,12 +47,14 @@ __global__ void coefficients_kernel(SubDev *subs, int nsubs, float2 *coef32, dou
     }
     if (coef32) {
         float2 *t32 = coef32 + S.coef32[a];
+        double2 *th = coefh ? coefh + S.coef32[a] : nullptr;
         const int m = (n - 1) / 2;
         const int cb = n - 1 - m;
         double d = b_end, d_m1 = 0.0, d_cb1 = 0.0;
         for (int t = 0; t < cb; ++t) {
             if (t > 0) d = b_in - c * c / d;
             t32[t] = make_float2((float)(f / d), (float)(c / d));
+            if (th) th[t] = make_double2(f / d, c / d);
             if (t == m - 1) d_m1 = d;
             if (t == cb - 1) d_cb1 = d;
         }
@@ -60,16 +64,18 @@ __global__ void coefficients_kernel(SubDev *subs, int nsubs, float2 *coef32, dou
         if (cb > 0) gamma -= c * c / d_cb1;
         S.mid32[a][0] = (float)(f / gamma);
         S.mid32[a][1] = (float)(c / gamma);
+        S.mid64[a][0] = f / gamma;
+        S.mid64[a][1] = c / gamma;
     }
 }
 
-hipError_t launch_coefficients(const SubDev *, int nsubs, float2 *coef32, double2 *coef64,
+hipError_t launch_coefficients(const SubDev *, int nsubs, float2 *coef32, double2 *coefh, double2 *coef64,
                                SubDev *subs_rw, hipStream_t st)
 {
     const int threads = nsubs * 3;
     if (threads == 0) return hipSuccess;
     hipLaunchKernelGGL(coefficients_kernel, dim3((threads + 127) / 128), dim3(128), 0, st,
-                       subs_rw, nsubs, coef32, coef64);
+                       subs_rw, nsubs, coef32, coefh, coef64);
     return hipGetLastError();
 }
 

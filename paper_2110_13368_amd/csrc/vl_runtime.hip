@@ -153,7 +153,8 @@ struct vl_ctx {
     int wait_limit_us = 2000000;  // a tile of the one-launch step waits at most this long
 
     // workspace layout (byte offsets)
-    size_t o_subs = 0, o_coef32 = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0, o_xl32 = 0;
+    size_t o_subs = 0, o_coef32 = 0, o_coefh = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0,
+           o_xl32 = 0;
     size_t o_cells = 0, o_occ_prefix = 0, o_occ_vox = 0, o_seg_start = 0, o_comp = 0, o_ab = 0;
     size_t o_pos = 0, o_V = 0, o_S = 0, o_U = 0, o_RS = 0, o_keys = 0, o_seg_id = 0;
     size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
@@ -312,7 +313,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
     int rc;
     if (ctx->precision == VL_F32) {
         float *field = (float *)ctx->field;
-        const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+        const double2 *coef = ctx->at<double2>(ctx->o_coefh);
         const bool fused = ctx->fuse_sources >= 1 && total_occ > 0;
         const vl::FusedSources src{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
                                    ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), fused ? 1 : 0,
@@ -942,6 +943,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     };
     ctx->o_subs = take(sizeof(SubDev) * nsubs);
     ctx->o_coef32 = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->n_coef32 : 0);
+    ctx->o_coefh = take(ctx->precision == VL_F32 ? sizeof(double2) * ctx->n_coef32 : 0);
     ctx->o_coef64 = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->n_coef64 : 0);
     ctx->o_xl32 = take(ctx->precision == VL_F32 ? sizeof(float) * ctx->n_xl32 : 0);
     ctx->o_itable = take(sizeof(int) * ctx->itable.size());
@@ -1012,6 +1014,7 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
                           hipMemcpyHostToDevice, st));
     VL_HIP(vl::launch_coefficients(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(),
                                    ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
+                                   ctx->precision == VL_F32 ? ctx->at<double2>(ctx->o_coefh) : nullptr,
                                    ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
                                    ctx->at<SubDev>(ctx->o_subs), st));
     if (ctx->precision == VL_F32)
@@ -1057,6 +1060,7 @@ int vl_update_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D, const
                           sizeof(SubDev) * n_sub, hipMemcpyHostToDevice, st));
     VL_HIP(vl::launch_coefficients(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(),
                                    ctx->precision == VL_F32 ? ctx->at<float2>(ctx->o_coef32) : nullptr,
+                                   ctx->precision == VL_F32 ? ctx->at<double2>(ctx->o_coefh) : nullptr,
                                    ctx->precision == VL_F64 ? ctx->at<double2>(ctx->o_coef64) : nullptr,
                                    ctx->at<SubDev>(ctx->o_subs), st));
     if (ctx->precision == VL_F32)
@@ -1731,7 +1735,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
 {
     hipStream_t st = ctx->stream;
     const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
-    const float2 *coef = ctx->at<float2>(ctx->o_coef32);
+    const double2 *coef = ctx->at<double2>(ctx->o_coefh);
     float *field = (float *)ctx->field;
     const vl::FusedSources nosrc{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
                                  ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0, 0};

@@ -25,7 +25,8 @@
 // both waves works on line l.  Each wave walks its rows in one direction with
 // a wave-uniform row offset, so y- and z-lines (stride nx, nx*ny) are read and
 // written as 256-byte rows of 64 neighbouring x values.  x-lines are
-// contiguous: they are moved through a 64x65 LDS block per 64 columns, loaded
+// contiguous: they are moved through a 64x65 LDS block per 64 columns (64x33
+// per 32 columns for lines of up to 65 voxels), loaded
 // with lanes along x and read back with lanes along the lines.  The half line
 // a lane owns stays in VGPRs (CAP values).
 #include "vl_device.h"
@@ -37,13 +38,15 @@ namespace vl {
 // volume's tiles of this axis.  Called by every thread of a 128-thread
 // workgroup (it contains workgroup barriers).
 template <int AXIS, int CAP, bool XSTAGE>
-__device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const float2 *__restrict__ coef,
+__device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const double2 *__restrict__ coef,
                                            float *__restrict__ field, float *__restrict__ raw,
-                                           const FusedSources &src, TileLds<CAP, XSTAGE> &sh)
+                                           const FusedSources &src, FwdLds<CAP, XSTAGE> &sh)
 {
-    constexpr int kChunks = (CAP + 63) / 64;
-    float(&xch)[2][kWave] = sh.xch;
-    float2 *cs_lds = sh.piv;
+    constexpr int kW = XStage<CAP>::W;    // stage columns per chunk
+    constexpr int kSX = XStage<CAP>::SX;  // stage row stride
+    constexpr int kChunks = (CAP + kW - 1) / kW;
+    double(&xch)[2][kWave] = sh.xch;
+    double2 *cs_lds = sh.piv;
     float *stage = sh.stage;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -55,13 +58,13 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     const int m = (n - 1) >> 1;    // middle row
     const int cb = n - 1 - m;      // rows below the middle (m or m + 1)
     const int nel = top ? m : cb;  // rows this wave eliminates and holds
-    const float g1 = S.mid32[AXIS][0];
-    const float g2 = S.mid32[AXIS][1];
+    const double g1 = S.mid64[AXIS][0];
+    const double g2 = S.mid64[AXIS][1];
     const int dmask = S.dir_mask;
 
-    // pivot table (inv_d_t, c/d_t), t < cb, staged once per workgroup
+    // pivot table (inv_d_t, c/d_t), t < cb, FP64, staged once per workgroup
     {
-        const float2 *__restrict__ cf = coef + S.coef32[AXIS];
+        const double2 *__restrict__ cf = coef + S.coef32[AXIS];
         for (int t = threadIdx.x; t < cb && t < CAP; t += 128) cs_lds[t] = cf[t];
     }
 
@@ -120,32 +123,36 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
 
     // ---- load the half line (local t: wave 0 row t, wave 1 row n-1-t) ----
     if (AXIS == 0 && XWide<CAP>::value) {
-        x_load_wide<CAP>(v, rs, stage + wave * 64 * 65, top, n, nel, row_b, xrows_left, lane);
+        x_load_wide<CAP>(v, rs, stage + wave * 64 * kSX, top, n, nel, row_b, xrows_left, lane);
     } else if (AXIS == 0) {
-        float *st = stage + wave * 64 * 65;
+        float *st = stage + wave * 64 * kSX;
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            if (c * 64 < nel) {
-                const int cs = top ? c * 64 : n - 64 * (c + 1);
+            if (c * kW < nel) {
+                const int cs = top ? c * kW : n - kW * (c + 1);
                 const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
                 const unsigned cb4 = (unsigned)col * 4u;
                 // DMA straight into LDS: lane j's value of row q lands in
-                // st[q*65 + j]; no VGPR staging, all 64 rows in flight.
+                // st[q*kSX + j]; no VGPR staging, all 64 rows in flight.  With
+                // 32-column chunks only lanes 0-31 take part (the DMA writes
+                // lane j at the row's start + j).
+                if (kW == 64 || lane < kW) {
 #pragma unroll
-                for (int q = 0; q < 64; ++q)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        rs, (__attribute__((address_space(3))) void *)(st + q * 65), 4, (int)cb4,
-                        min(q, xrows_left - 1) * row_b, 0, 0);
+                    for (int q = 0; q < 64; ++q)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            rs, (__attribute__((address_space(3))) void *)(st + q * kSX), 4, (int)cb4,
+                            min(q, xrows_left - 1) * row_b, 0, 0);
+                }
                 __builtin_amdgcn_s_waitcnt(0);
                 wave_sync_lds();
                 if (top) {
 #pragma unroll
-                    for (int jj = 0; jj < 64; ++jj)
-                        if (c * 64 + jj < CAP && c * 64 + jj < nel) v[c * 64 + jj] = st[lane * 65 + jj];
+                    for (int jj = 0; jj < kW; ++jj)
+                        if (c * kW + jj < CAP && c * kW + jj < nel) v[c * kW + jj] = st[lane * kSX + jj];
                 } else {
 #pragma unroll
-                    for (int jj = 0; jj < 64; ++jj)
-                        if (c * 64 + jj < CAP && c * 64 + jj < nel) v[c * 64 + jj] = st[lane * 65 + 63 - jj];
+                    for (int jj = 0; jj < kW; ++jj)
+                        if (c * kW + jj < CAP && c * kW + jj < nel) v[c * kW + jj] = st[lane * kSX + kW - 1 - jj];
                 }
                 wave_sync_lds();
             }
@@ -174,15 +181,20 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
     }
 
     // ---- elimination from this wave's end towards the middle ----
-    float prev = 0.f;
+    // The recurrences run in FP64 and only the values they store are rounded
+    // to FP32: rounding inside an FP32 recurrence is the same for
+    // neighbouring lines of a smooth field and from one step to the next, so
+    // it accumulates like a bias (a drift of the mean of about 3 ulp per 100
+    // steps), while rounding the stored values does not.
+    double prev = 0.0;
     VL_FOR_UP(CAP, nel, t, {
-        const float2 c = cs_lds[t];
-        prev = fmaf(c.y, prev, v[t] * c.x);
-        v[t] = prev;
+        const double2 c = cs_lds[t];
+        prev = fma(c.y, prev, (double)v[t] * c.x);
+        v[t] = (float)prev;
     })
 
     // ---- middle row ----
-    float xm = 0.f;
+    double xm = 0.0;
     if (!top) xch[0][lane] = prev;  // z_{m+1} (0 when the line has one row)
     __syncthreads();
     if (top) {
@@ -196,54 +208,57 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
         } else {
             rm = bload(rs, lane_b, m * row_b);
         }
-        xm = fmaf(g2, prev + xch[0][lane], rm * g1);
+        xm = fma(g2, prev + xch[0][lane], (double)rm * g1);
         xch[1][lane] = xm;
     }
     __syncthreads();
     if (!top) xm = xch[1][lane];
 
     // ---- back-substitution from the middle outwards ----
-    float nxt = xm;
+    double nxt = xm;
     VL_FOR_DOWN(CAP, nel, t, {
-        nxt = fmaf(cs_lds[t].y, nxt, v[t]);
-        v[t] = nxt;
+        nxt = fma(cs_lds[t].y, nxt, (double)v[t]);
+        v[t] = (float)nxt;
     })
+    float xm32 = (float)xm;
 
     // ---- raw solve output before the Dirichlet projection (adjoint replay) ----
     if (raw != nullptr) {
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw + base, S.base + S.vol - base);
         if (AXIS == 0 && XWide<CAP>::value) {
-            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm);
-            x_store_wide<CAP>(v, rr, stage + wave * 64 * 65, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
+            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm32);
+            x_store_wide<CAP>(v, rr, stage + wave * 64 * kSX, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
         } else if (AXIS == 0) {
             // through the LDS stage, like the field store below
-            float *st = stage + wave * 64 * 65;
-            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm);
+            float *st = stage + wave * 64 * kSX;
+            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm32);
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
-                if (c * 64 < nel) {
+                if (c * kW < nel) {
                     if (top) {
 #pragma unroll
-                        for (int jj = 0; jj < 64; ++jj)
-                            if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + jj] = v[c * 64 + jj];
+                        for (int jj = 0; jj < kW; ++jj)
+                            if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + jj] = v[c * kW + jj];
                     } else {
 #pragma unroll
-                        for (int jj = 0; jj < 64; ++jj)
-                            if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + 63 - jj] = v[c * 64 + jj];
+                        for (int jj = 0; jj < kW; ++jj)
+                            if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + kW - 1 - jj] = v[c * kW + jj];
                     }
                     wave_sync_lds();
-                    const int cs = top ? c * 64 : n - 64 * (c + 1);
+                    const int cs = top ? c * kW : n - kW * (c + 1);
                     const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
                     const int so = col - cs;
                     const unsigned cb4 = (unsigned)col * 4u;
+                    // with 32-column chunks lanes 32-63 have no column of
+                    // their own (the bottom wave's would lie past the line)
 #pragma unroll 16
                     for (int q = 0; q < 64; ++q)
-                        if (q < xrows_left) bstore(rr, cb4, q * row_b, st[q * 65 + so]);
+                        if (q < xrows_left && (kW == 64 || lane < kW)) bstore(rr, cb4, q * row_b, st[q * kSX + so]);
                     wave_sync_lds();
                 }
             }
         } else {
-            if (top) bstore(rr, lane_b, m * row_b, xm);
+            if (top) bstore(rr, lane_b, m * row_b, xm32);
             const int row0 = top ? 0 : (n - 1) * row_b;
             const int step = top ? row_b : -row_b;
             VL_FOR_UP(CAP, nel, t, bstore(rr, lane_b, row0 + t * step, v[t]);)
@@ -255,7 +270,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
         const float wv = face_value(S.dval32, wface);
         const bool whole = wface >= 0;
         VL_FOR_UP(CAP, nel, t, v[t] = whole ? wv : v[t];)
-        xm = whole ? wv : xm;
+        xm32 = whole ? wv : xm32;
     }
     if (top) {
         if (f_first >= 0) {
@@ -263,7 +278,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
             if (m >= 1)
                 v[0] = ev;
             else
-                xm = ev;
+                xm32 = ev;
         }
     } else if (cb >= 1 && f_last >= 0) {
         v[0] = face_value(S.dval32, f_last);
@@ -271,36 +286,36 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
 
     // ---- store ----
     if (AXIS == 0 && XWide<CAP>::value) {
-        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm);
-        x_store_wide<CAP>(v, rs, stage + wave * 64 * 65, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
+        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
+        x_store_wide<CAP>(v, rs, stage + wave * 64 * kSX, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
     } else if (AXIS == 0) {
-        float *st = stage + wave * 64 * 65;
-        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm);
+        float *st = stage + wave * 64 * kSX;
+        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            if (c * 64 < nel) {
+            if (c * kW < nel) {
                 if (top) {
 #pragma unroll
-                    for (int jj = 0; jj < 64; ++jj)
-                        if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + jj] = v[c * 64 + jj];
+                    for (int jj = 0; jj < kW; ++jj)
+                        if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + jj] = v[c * kW + jj];
                 } else {
 #pragma unroll
-                    for (int jj = 0; jj < 64; ++jj)
-                        if (c * 64 + jj < CAP && c * 64 + jj < nel) st[lane * 65 + 63 - jj] = v[c * 64 + jj];
+                    for (int jj = 0; jj < kW; ++jj)
+                        if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + kW - 1 - jj] = v[c * kW + jj];
                 }
                 wave_sync_lds();
-                const int cs = top ? c * 64 : n - 64 * (c + 1);
+                const int cs = top ? c * kW : n - kW * (c + 1);
                 const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
                 const int so = col - cs;
                 const unsigned cb4 = (unsigned)col * 4u;
 #pragma unroll 16
                 for (int q = 0; q < 64; ++q)
-                    if (q < xrows_left) bstore(rs, cb4, q * row_b, st[q * 65 + so]);
+                    if (q < xrows_left && (kW == 64 || lane < kW)) bstore(rs, cb4, q * row_b, st[q * kSX + so]);
                 wave_sync_lds();
             }
         }
     } else {
-        if (top) bstore(rs, lane_b, m * row_b, xm);
+        if (top) bstore(rs, lane_b, m * row_b, xm32);
         const int row0 = top ? 0 : (n - 1) * row_b;
         const int step = top ? row_b : -row_b;
         VL_FOR_UP(CAP, nel, t, bstore(rs, lane_b, row0 + t * step, v[t]);)
@@ -333,10 +348,10 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const flo
 
 template <int AXIS, int CAP>
 __global__ void __launch_bounds__(128)
-sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
+sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const double2 *__restrict__ coef,
           float *__restrict__ field, float *__restrict__ raw, FusedSources src)
 {
-    __shared__ TileLds<CAP, AXIS == 0> sh;
+    __shared__ FwdLds<CAP, AXIS == 0> sh;
     const int tile = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int slot = find_slot(L.tile_prefix, L.count, tile);
     const int local = tile - L.tile_prefix[slot];
@@ -353,10 +368,10 @@ sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restri
 // workgroup to leave resets the counters for the next launch.
 template <int CAP>
 __global__ void __launch_bounds__(128)
-sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
+sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const double2 *__restrict__ coef,
                       float *__restrict__ field, FusedSources src)
 {
-    __shared__ TileLds<CAP, true> sh;
+    __shared__ FwdLds<CAP, true> sh;
     __shared__ int s_tile;
     unsigned *head = Q.counters;
     unsigned *exited = Q.counters + 1;
@@ -423,7 +438,7 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const float2
 
 template <int AXIS>
 static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *subs,
-                              const float2 *coef, float *field, float *raw, const FusedSources &src,
+                              const double2 *coef, float *field, float *raw, const FusedSources &src,
                               hipStream_t st)
 {
     const dim3 grid(L.total_tiles), block(128);
@@ -442,7 +457,7 @@ static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *s
 }
 
 hipError_t launch_step_persistent(int cap_idx, int grid, const StepQueue &Q, const SubDev *subs,
-                                  const float2 *coef, float *field, const FusedSources &src,
+                                  const double2 *coef, float *field, const FusedSources &src,
                                   hipStream_t st)
 {
     if (Q.phase_start[3] <= 0 || grid <= 0) return hipSuccess;
@@ -477,7 +492,7 @@ hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks)
 }
 
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,
-                            const float2 *coef, float *field, float *raw, const FusedSources &src,
+                            const double2 *coef, float *field, float *raw, const FusedSources &src,
                             hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;

@@ -26,8 +26,8 @@ constexpr int kXYBlock = 16;  // rows per block of LDS reads in the in-place sol
 // the second, as in the split solve of the sweep kernels); every wave runs
 // the same rounds so that the workgroup barriers line up.
 template <int AXIS>
-__device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, int SX, const float2 *piv,
-                                            float *xchg, __amdgpu_buffer_rsrc_t rp)
+__device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, int SX, const double2 *piv,
+                                            double *xchg, __amdgpu_buffer_rsrc_t rp)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -39,8 +39,8 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
     const int m = (n - 1) >> 1;
     const int cb = n - 1 - m;
     const int nel = top ? m : cb;
-    const float g1 = S.mid32[AXIS][0];
-    const float g2 = S.mid32[AXIS][1];
+    const double g1 = S.mid64[AXIS][0];
+    const double g2 = S.mid64[AXIS][1];
     const int dmask = S.dir_mask;
     const int lo_f = (dmask >> (2 * AXIS)) & 1 ? 2 * AXIS : -1;
     const int hi_f = (dmask >> (2 * AXIS + 1)) & 1 ? 2 * AXIS + 1 : -1;
@@ -48,7 +48,7 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
     // this pair's exchange slot per lane: the second-half wave leaves its last
     // eliminated value there, the first-half wave reads it and puts the middle
     // unknown in its place (the barriers separate the three accesses)
-    float *xs = xchg + pair * kWave;
+    double *xs = xchg + pair * kWave;
     // element t of this wave's half line: e_first + t*e_step from the line's
     // origin (x: along the row; y: down the column)
     const int unit = AXIS == 0 ? 1 : SX;
@@ -86,7 +86,7 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
         //      per-row tests, only the last (partial) block does ----
         float *E0 = L0 + e_first;
         const int nfull = nel / kXYBlock;
-        float prev = 0.f;
+        double prev = 0.0;  // FP64 recurrences, as in the sweep kernels
         if (active) {
             const bool end_d = AXIS == 0 && (top ? lo_f : hi_f) >= 0;
             const float end_v = end_d ? S.dval32[top ? lo_f : hi_f] : 0.f;
@@ -98,9 +98,9 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
                 if (b == 0 && end_d) r[0] = end_v;
 #pragma unroll
                 for (int e = 0; e < kXYBlock; ++e) {
-                    const float2 c = piv[t0 + e];
-                    prev = fmaf(c.y, prev, r[e] * c.x);
-                    r[e] = prev;
+                    const double2 c = piv[t0 + e];
+                    prev = fma(c.y, prev, (double)r[e] * c.x);
+                    r[e] = (float)prev;
                 }
                 if (valid) {
 #pragma unroll
@@ -117,9 +117,9 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
 #pragma unroll
                 for (int e = 0; e < kXYBlock; ++e) {
                     if (t0 + e < nel) {
-                        const float2 c = piv[t0 + e];
-                        prev = fmaf(c.y, prev, r[e] * c.x);
-                        r[e] = prev;
+                        const double2 c = piv[t0 + e];
+                        prev = fma(c.y, prev, (double)r[e] * c.x);
+                        r[e] = (float)prev;
                     }
                 }
                 if (valid) {
@@ -132,14 +132,14 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
         }
         __syncthreads();
         // ---- middle row (the first-half wave keeps it in a register) ----
-        float xm = 0.f;
+        double xm = 0.0;
         if (active && top) {
             float rm = L0[e_mid];
             if (AXIS == 0 && m == 0) {
                 const int f0 = max(lo_f, n == 1 ? hi_f : -1);
                 if (f0 >= 0) rm = S.dval32[f0];
             }
-            xm = fmaf(g2, prev + xs[lane], rm * g1);
+            xm = fma(g2, prev + xs[lane], (double)rm * g1);
             xs[lane] = xm;
         }
         __syncthreads();
@@ -149,10 +149,10 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
         //      a scalar register ----
         if (active) {
             if (!top) xm = xs[lane];
-            float nxt = xm;
+            double nxt = xm;
             const unsigned col_b = (unsigned)line * 4u;
             if (top && valid) {
-                float out = whole ? wv : xm;
+                float out = whole ? wv : (float)xm;
                 if (m == 0 && f_first >= 0) out = face_value(S.dval32, f_first);
                 if (AXIS == 0)
                     L0[e_mid] = out;
@@ -171,8 +171,8 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
 #pragma unroll
                     for (int e = kXYBlock - 1; e >= 0; --e) {
                         if (t0 + e < nel) {
-                            nxt = fmaf(piv[t0 + e].y, nxt, y[e]);
-                            y[e] = whole ? wv : nxt;
+                            nxt = fma(piv[t0 + e].y, nxt, (double)y[e]);
+                            y[e] = whole ? wv : (float)nxt;
                         }
                     }
                     if (t0 == 0 && end_p) y[0] = end_out;
@@ -196,8 +196,8 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
                 for (int e = 0; e < kXYBlock; ++e) y[e] = E0[(t0 + e) * e_step];
 #pragma unroll
                 for (int e = kXYBlock - 1; e >= 0; --e) {
-                    nxt = fmaf(piv[t0 + e].y, nxt, y[e]);
-                    y[e] = whole ? wv : nxt;
+                    nxt = fma(piv[t0 + e].y, nxt, (double)y[e]);
+                    y[e] = whole ? wv : (float)nxt;
                 }
                 if (b == 0 && end_p) y[0] = end_out;
                 if (valid) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void plane_solve(const SubDev &S, int k, float *P, in
 }
 
 __global__ void __launch_bounds__(kXYThreads)
-sweep_xy_plane(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__restrict__ coef,
+sweep_xy_plane(SweepLaunch L, const SubDev *__restrict__ subs, const double2 *__restrict__ coef,
                float *__restrict__ field)
 {
     extern __shared__ __attribute__((aligned(16))) float xy_lds[];
@@ -228,10 +228,10 @@ sweep_xy_plane(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__r
     const int cbx = nx - 1 - (nx - 1) / 2, cby = ny - 1 - (ny - 1) / 2;
     // LDS: x and y pivot tables, one exchange slot per lane of each wave
     // pair, then the plane (sized by xy_lds_bytes)
-    float2 *pivx = reinterpret_cast<float2 *>(xy_lds);
-    float2 *pivy = pivx + cbx;
-    float *xchg = reinterpret_cast<float *>(pivy + cby);
-    float *P = xchg + (kXYThreads / 2);
+    double2 *pivx = reinterpret_cast<double2 *>(xy_lds);
+    double2 *pivy = pivx + cbx;
+    double *xchg = reinterpret_cast<double *>(pivy + cby);
+    float *P = reinterpret_cast<float *>(xchg + (kXYThreads / 2));
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const long long pbase = S.base + (long long)k * nx * ny;
@@ -246,8 +246,8 @@ sweep_xy_plane(SweepLaunch L, const SubDev *__restrict__ subs, const float2 *__r
                     rp, (__attribute__((address_space(3))) void *)(P + j * SX + c * kWave), 4,
                     (j * nx + c * kWave + lane) * 4, 0, 0, 0);
     {
-        const float2 *__restrict__ cfx = coef + S.coef32[0];
-        const float2 *__restrict__ cfy = coef + S.coef32[1];
+        const double2 *__restrict__ cfx = coef + S.coef32[0];
+        const double2 *__restrict__ cfy = coef + S.coef32[1];
         for (int t = threadIdx.x; t < cbx; t += kXYThreads) pivx[t] = cfx[t];
         for (int t = threadIdx.x; t < cby; t += kXYThreads) pivy[t] = cfy[t];
     }
@@ -265,7 +265,7 @@ hipError_t prepare_sweep_xy(size_t lds_bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev *subs, const float2 *coef,
+hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev *subs, const double2 *coef,
                            float *field, hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;

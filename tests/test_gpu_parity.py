@@ -428,7 +428,7 @@ def _run_xy(specs, steps, fuse_xy, decay=vb.VL_DECAY_ONCE):
 
 
 @pytest.mark.parametrize("decay", [vb.VL_DECAY_ONCE, vb.VL_DECAY_THIRDS])
-@pytest.mark.parametrize("shape,bc", [((200, 200, 5), "mixed"), ((199, 57, 9), "dirichlet"), ((64, 130, 6), "mixed"),
+@pytest.mark.parametrize("shape,bc", [((199, 199, 5), "mixed"), ((199, 57, 9), "dirichlet"), ((64, 130, 6), "mixed"),
                                       ((1, 40, 7), "mixed"), ((45, 1, 3), "dirichlet"), ((3, 2, 4), "mixed"),
                                       ((2, 3, 1), "dirichlet"), ((129, 65, 2), "neumann")])
 def test_xy_plane_kernel_equals_separate_sweeps(shape, bc, decay):
