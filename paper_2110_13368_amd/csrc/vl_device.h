@@ -71,6 +71,19 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
 }
+// The same with a cache policy (the instruction's aux bits): kNonTemporal
+// marks streaming accesses whose lines will not be touched again soon.
+constexpr int kNonTemporal = 2;
+template <int POL>
+__device__ __forceinline__ float bload_p(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, POL));
+}
+template <int POL>
+__device__ __forceinline__ void bstore_p(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, POL);
+}
 typedef unsigned vl_u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned vl_u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float4 v)

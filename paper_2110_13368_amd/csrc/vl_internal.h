@@ -159,17 +159,21 @@ hipError_t launch_sweep_xy(const SweepLaunch &L, size_t lds_bytes, const SubDev 
 // a3 with lanes along the line: tables (one 64-thread workgroup per volume,
 // FP64 arithmetic) and the sweep for lines of K voxels per lane (tiles of 64
 // x-lines as for the split sweep).  raw as for launch_sweep_f32.
-hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *coef_unused, float *xl32,
+// The tables are written twice: in FP64 (xl64) for the forward solve, whose
+// arithmetic is FP64, and in FP32 (xl32) for the adjoint's reverse solve.
+hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *coef_unused, float *xl32, double *xl64,
                             hipStream_t st);
-hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *field,
+hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const double *xl64, float *field,
                            float *raw, const CarriedSources &carry, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
 // raw (may be null, same layout as the field) receives each solve's output
-// before the Dirichlet projection, for the adjoint's replay.
+// before the Dirichlet projection, for the adjoint's replay.  nontemporal (z
+// only): stream the rows with non-temporal loads and stores, for launches
+// none of whose tiles applies cell sources after its stores.
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
                             const SubDev *subs, const double2 *coef, float *field, float *raw,
-                            const FusedSources &src, hipStream_t st);
+                            const FusedSources &src, bool nontemporal, hipStream_t st);
 
 // a9: adjoint sweep along axis, in place on w (same layout as the field).  The
 // Dirichlet adjoint (zero at Dirichlet voxels) is applied on load and store;
@@ -209,24 +213,32 @@ hipError_t launch_dirichlet_plain(const SubDev *subs, const int4 *faces, int nfa
 hipError_t launch_decay_plain(const SubDev *subs, int nsubs, const long long *vox_prefix,
                               long long total, double *field, hipStream_t st);
 
-// a2: cell binning.
+// a2: cell binning.  The counts of an upload live on the device (counts[0]
+// out of domain, [1] occupied voxels, [2] inside, [4] cells), so the binning
+// kernels run back to back without reading counts on the host; n_cap (the
+// upload's cell count) bounds them and sizes the grids.
+hipError_t launch_upload_counts(int *counts, int n, hipStream_t st);
 hipError_t launch_cell_keys(const double *pos, int n, int nx, int ny, int nz, double x0,
                             double y0, double z0, double dx, double dy, double dz,
-                            unsigned long long *keys, int n_pad, int *n_out,
-                            hipStream_t st);
-hipError_t launch_bitonic_sort(unsigned long long *keys, int n_pad, hipStream_t st);
-hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id,
-                           int *occ_vox, int *seg_start, int *n_occ, hipStream_t st);
-hipError_t launch_composites(const unsigned long long *keys, const int *seg_start,
-                             int n_occ, int ns, const double *V, const double *S,
-                             const double *U, const double *RS, double dt, double vvox,
-                             const int *pos, float2 *comp32, float2 *comp32_v, int v_stride,
-                             double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st);
-hipError_t launch_xline_starts(const int *occ_vox_v, int n_occ, int nx, int nlines, int *line_start,
+                            unsigned long long *keys, int *n_out, hipStream_t st);
+// Stable radix sort of *n_dev (<= n_cap) keys on bits [lo_bit, lo_bit + bits)
+// (rounded up to whole pairs of 4-bit digits), ping-ponging with alt; hist
+// holds radix_hist_entries(n_cap) entries.
+int radix_hist_entries(int n_cap);
+hipError_t launch_radix_sort(unsigned long long *keys, unsigned long long *alt, int n_cap, const int *n_dev,
+                             int lo_bit, int bits, unsigned *hist, hipStream_t st);
+// scratch: radix_hist_entries(n_cap) entries (the sort's hist serves)
+hipError_t launch_segments(const unsigned long long *keys, int n_cap, int n, int *seg_id, int *occ_vox,
+                           int *seg_start, int *counts, unsigned *scratch, hipStream_t st);
+hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, const int *counts, int n_cap,
+                             int ns, const double *V, const double *S, const double *U, const double *RS,
+                             double dt, double vvox, const int *pos, float2 *comp32, float2 *comp32_v,
+                             int v_stride, double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st);
+hipError_t launch_xline_starts(const int *occ_vox_v, const int *counts, int nx, int nlines, int *line_start,
                                hipStream_t st);
-hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
-                              unsigned long long *zkeys, int *occ_vox, int *pos, int *line_start,
-                              hipStream_t st);
+hipError_t launch_zline_order(const int *occ_vox_v, const int *counts, int n_cap, int nxy, int nz,
+                              unsigned long long *zkeys, unsigned long long *zalt, unsigned *hist, int *occ_vox,
+                              int *pos, int *line_start, hipStream_t st);
 
 // a5/a6: sources over the occupied voxels of every simulation.
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix,

@@ -224,14 +224,10 @@ constexpr unsigned long long kNoVoxel = ~0ull;
 
 __global__ void cell_keys_kernel(const double *__restrict__ pos, int n, int nx, int ny, int nz,
                                  double x0, double y0, double z0, double dx, double dy, double dz,
-                                 unsigned long long *__restrict__ keys, int n_pad, int *n_out)
+                                 unsigned long long *__restrict__ keys, int *n_out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pad) return;
-    if (i >= n) {
-        keys[i] = kNoVoxel;
-        return;
-    }
+    if (i >= n) return;
     const double lo[3] = {x0, y0, z0}, h[3] = {dx, dy, dz};
     const int nn[3] = {nx, ny, nz};
     long long idx[3];
@@ -252,154 +248,267 @@ __global__ void cell_keys_kernel(const double *__restrict__ pos, int n, int nx, 
 
 hipError_t launch_cell_keys(const double *pos, int n, int nx, int ny, int nz, double x0, double y0,
                             double z0, double dx, double dy, double dz, unsigned long long *keys,
-                            int n_pad, int *n_out, hipStream_t st)
+                            int *n_out, hipStream_t st)
 {
-    if (n_pad <= 0) return hipSuccess;
-    hipLaunchKernelGGL(cell_keys_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st, pos, n, nx, ny,
-                       nz, x0, y0, z0, dx, dy, dz, keys, n_pad, n_out);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cell_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, nx, ny,
+                       nz, x0, y0, z0, dx, dy, dz, keys, n_out);
     return hipGetLastError();
 }
 
-// Bitonic sorting network (Batcher 1968) over n_pad = 2^p keys: for each
-// stage size k and distance j, element i is compared with i ^ j.  Keys are
-// unique, so the order is fully determined.
-__global__ void bitonic_global_kernel(unsigned long long *keys, int n_pad, int j, int k)
+// Stable LSD radix sort of 64-bit keys on bits [lo, lo + 4*passes): least
+// significant digit first, each pass a stable counting sort of one 4-bit digit
+// (Knuth, The Art of Computer Programming vol. 3, section 5.2.5).  Blocks of
+// kRsTile consecutive keys: per-block digit counts, one exclusive scan over
+// (digit, block) in digit-major order, then each block writes its keys to
+// their places in key order, which keeps equal digits in their input order.
+// The key count is read on the device (*n_dev, at most n_cap, which sizes the
+// grids), so a count produced by an earlier kernel needs no trip to the host.
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRsRadix = 16;
+
+__global__ void __launch_bounds__(kRsThreads)
+rs_hist_kernel(const unsigned long long *__restrict__ keys, const int *__restrict__ n_dev, int shift,
+               unsigned *__restrict__ hist, int nblocks)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pad) return;
-    const int l = i ^ j;
-    if (l <= i) return;
-    const unsigned long long a = keys[i], b = keys[l];
-    const bool up = (i & k) == 0;
-    if ((a > b) == up) {
-        keys[i] = b;
-        keys[l] = a;
+    __shared__ unsigned cnt[kRsRadix];
+    const int n = *n_dev;
+    if (threadIdx.x < kRsRadix) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kRsTile;
+    for (int i = threadIdx.x; i < kRsTile; i += kRsThreads) {
+        const int g = base + i;
+        if (g < n) atomicAdd(&cnt[(unsigned)(keys[g] >> shift) & (kRsRadix - 1)], 1u);
     }
+    __syncthreads();
+    if (threadIdx.x < kRsRadix) hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// All distances j < 2048 of one stage k inside one block of 1024 threads
-// holding 2048 keys in LDS.
-__global__ void __launch_bounds__(1024) bitonic_local_kernel(unsigned long long *keys, int n_pad,
-                                                             int k_from, int k_to, int j_from)
+// In-place exclusive scan of a[0..m) by one workgroup; *total (if given)
+// receives the sum.
+__global__ void __launch_bounds__(1024) scan_small_kernel(unsigned *__restrict__ a, int m, int *total)
 {
-    __shared__ unsigned long long s[2048];
-    const int base = blockIdx.x * 2048;
-    for (int t = threadIdx.x; t < 2048; t += 1024) s[t] = keys[base + t];
+    __shared__ unsigned part[1024];
+    const int per = (m + 1023) / 1024;
+    const int b = min(m, (int)threadIdx.x * per), e = min(m, b + per);
+    unsigned sum = 0;
+    for (int i = b; i < e; ++i) sum += a[i];
+    part[threadIdx.x] = sum;
     __syncthreads();
-    for (int k = k_from; k <= k_to; k <<= 1) {
-        for (int j = (k == k_from ? j_from : k >> 1); j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < 2048; t += 1024) {
-                const int l = t ^ j;
-                if (l > t) {
-                    const unsigned long long a = s[t], b = s[l];
-                    const bool up = ((base + t) & k) == 0;
-                    if ((a > b) == up) {
-                        s[t] = b;
-                        s[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int i = b; i < e; ++i) {
+        const unsigned h = a[i];
+        a[i] = run;
+        run += h;
+    }
+    if (total && threadIdx.x == 1023) *total = (int)part[1023];
+}
+
+// c[d][t]: thread t's count of digit d on entry, its exclusive prefix over the
+// block's threads on exit (16 digits x 16 segments of 16 threads: each thread
+// sums one segment, one thread per digit scans the segment sums).
+__device__ __forceinline__ void rs_block_prefix(unsigned (&c)[kRsRadix][kRsThreads],
+                                                unsigned (&seg)[kRsRadix][kRsThreads / kRsRadix])
+{
+    constexpr int kSeg = kRsThreads / kRsRadix;
+    const int t = threadIdx.x;
+    const int r = t / kSeg, q = t % kSeg;
+    unsigned sum = 0;
+    for (int j = 0; j < kSeg; ++j) sum += c[r][q * kSeg + j];
+    seg[r][q] = sum;
+    __syncthreads();
+    if (t < kRsRadix) {
+        unsigned run = 0;
+        for (int j = 0; j < kSeg; ++j) {
+            const unsigned v = seg[t][j];
+            seg[t][j] = run;
+            run += v;
         }
     }
-    for (int t = threadIdx.x; t < 2048; t += 1024) keys[base + t] = s[t];
+    __syncthreads();
+    unsigned run = seg[r][q];
+    for (int j = 0; j < kSeg; ++j) {
+        const unsigned v = c[r][q * kSeg + j];
+        c[r][q * kSeg + j] = run;
+        run += v;
+    }
+    __syncthreads();
 }
 
-hipError_t launch_bitonic_sort(unsigned long long *keys, int n_pad, hipStream_t st)
+// Thread t holds keys t*kRsItems .. of its block's tile, in order; the keys of
+// one digit land after those of earlier blocks and earlier threads.
+__global__ void __launch_bounds__(kRsThreads)
+rs_scatter_kernel(const unsigned long long *__restrict__ in, unsigned long long *__restrict__ out,
+                  const int *__restrict__ n_dev, int shift, const unsigned *__restrict__ offs, int nblocks)
 {
-    if (n_pad <= 1) return hipSuccess;
-    if (n_pad < 2048) {
-        for (int k = 2; k <= n_pad; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1)
-                hipLaunchKernelGGL(bitonic_global_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st,
-                                   keys, n_pad, j, k);
-        return hipGetLastError();
+    __shared__ unsigned c[kRsRadix][kRsThreads];
+    __shared__ unsigned seg[kRsRadix][kRsThreads / kRsRadix];
+    const int n = *n_dev;
+    const int t = threadIdx.x;
+    const int base = blockIdx.x * kRsTile + t * kRsItems;
+    for (int d = 0; d < kRsRadix; ++d) c[d][t] = 0;
+    unsigned long long k[kRsItems];
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        const int g = base + j;
+        k[j] = g < n ? in[g] : 0ull;
+        if (g < n) ++c[(unsigned)(k[j] >> shift) & (kRsRadix - 1)][t];
     }
-    const int nb = n_pad / 2048;
-    // stages k <= 2048 entirely in LDS
-    hipLaunchKernelGGL(bitonic_local_kernel, dim3(nb), dim3(1024), 0, st, keys, n_pad, 2, 2048, 1);
-    for (int k = 4096; k <= n_pad; k <<= 1) {
-        for (int j = k >> 1; j >= 2048; j >>= 1)
-            hipLaunchKernelGGL(bitonic_global_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st,
-                               keys, n_pad, j, k);
-        hipLaunchKernelGGL(bitonic_local_kernel, dim3(nb), dim3(1024), 0, st, keys, n_pad, k, k, 1024);
+    __syncthreads();
+    rs_block_prefix(c, seg);
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        if (base + j < n) {
+            const unsigned d = (unsigned)(k[j] >> shift) & (kRsRadix - 1);
+            out[offs[d * nblocks + blockIdx.x] + c[d][t]++] = k[j];
+        }
+    }
+}
+
+int radix_hist_entries(int n_cap) { return kRsRadix * ((max(n_cap, 1) + kRsTile - 1) / kRsTile); }
+
+hipError_t launch_radix_sort(unsigned long long *keys, unsigned long long *alt, int n_cap, const int *n_dev, int lo_bit,
+                             int bits, unsigned *hist, hipStream_t st)
+{
+    if (n_cap <= 0 || bits <= 0) return hipSuccess;
+    int passes = (bits + 3) / 4;
+    passes += passes & 1;  // an even number of passes leaves the result in keys
+    if (lo_bit < 0 || lo_bit + 4 * passes > 64) return hipErrorInvalidValue;
+    const int nb = (n_cap + kRsTile - 1) / kRsTile;
+    unsigned long long *src = keys, *dst = alt;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = lo_bit + 4 * p;
+        hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(kRsThreads), 0, st, src, n_dev, shift, hist, nb);
+        hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(1024), 0, st, hist, kRsRadix * nb, (int *)nullptr);
+        hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(kRsThreads), 0, st, src, dst, n_dev, shift, hist, nb);
+        unsigned long long *tmp = src;
+        src = dst;
+        dst = tmp;
     }
     return hipGetLastError();
 }
 
-// Occupied voxels of the sorted keys (the first n_in are inside the grid):
-// a single workgroup scans the "new voxel" flags in order, so segment ids,
-// occupied-voxel list and segment starts come out in ascending voxel order.
-__global__ void __launch_bounds__(1024) segments_kernel(const unsigned long long *__restrict__ keys,
-                                                        int n_in, int *__restrict__ seg_id,
-                                                        int *__restrict__ occ_vox,
-                                                        int *__restrict__ seg_start, int *n_occ)
+// Occupied voxels of the sorted keys (the first n_in, counts[2], are inside
+// the grid): each key that starts a new voxel is flagged, and the flags are
+// numbered by an exclusive scan over blocks of kRsTile keys (block counts, one
+// scan of the block counts, then each block's own scan), so segment ids, the
+// occupied-voxel list and each segment's first key come out in ascending
+// voxel order; counts[1] receives the number of occupied voxels.
+__device__ __forceinline__ unsigned new_voxel(const unsigned long long *__restrict__ keys, int p, int n)
 {
-    __shared__ int warp_sums[16];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
+    return p < n && (p == 0 || (keys[p] >> 24) != (keys[p - 1] >> 24));
+}
+
+__global__ void __launch_bounds__(kRsThreads) n_in_kernel(int n, int *counts)
+{
+    if (threadIdx.x == 0) counts[2] = n - counts[0];
+}
+
+// The counts of an upload: out of domain, occupied voxels and inside (filled
+// in by the kernels that follow) start at zero; counts[4] = n keys to sort.
+__global__ void upload_counts_kernel(int *counts, int n)
+{
+    if (threadIdx.x == 0) {
+        counts[0] = 0;
+        counts[1] = 0;
+        counts[2] = 0;
+        counts[4] = n;
+    }
+}
+
+hipError_t launch_upload_counts(int *counts, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(upload_counts_kernel, dim3(1), dim3(64), 0, st, counts, n);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kRsThreads)
+seg_count_kernel(const unsigned long long *__restrict__ keys, const int *__restrict__ counts,
+                 unsigned *__restrict__ bsum)
+{
+    __shared__ unsigned red[kRsThreads];
+    const int n = counts[2];
+    const int base = blockIdx.x * kRsTile;
+    unsigned c = 0;
+    for (int i = threadIdx.x; i < kRsTile; i += kRsThreads) c += new_voxel(keys, base + i, n);
+    red[threadIdx.x] = c;
     __syncthreads();
-    for (int base = 0; base < n_in; base += 1024) {
-        const int p = base + threadIdx.x;
-        int flag = 0;
-        if (p < n_in) flag = (p == 0) || ((keys[p] >> 24) != (keys[p - 1] >> 24));
-        // inclusive scan in the block: waves by shuffles, then wave sums
-        int x = flag;
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) warp_sums[w] = x;
+    for (int o = kRsThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int q = 0; q < 16; ++q) {
-                const int t = warp_sums[q];
-                warp_sums[q] = acc;
-                acc += t;
-            }
-        }
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kRsThreads)
+seg_write_kernel(const unsigned long long *__restrict__ keys, const int *__restrict__ counts,
+                 const unsigned *__restrict__ boff, int *__restrict__ seg_id, int *__restrict__ occ_vox,
+                 int *__restrict__ seg_start)
+{
+    __shared__ unsigned tsum[kRsThreads];
+    const int n = counts[2];
+    const int t = threadIdx.x;
+    const int base = blockIdx.x * kRsTile + t * kRsItems;
+    unsigned f[kRsItems], c = 0;
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        f[j] = new_voxel(keys, base + j, n);
+        c += f[j];
+    }
+    tsum[t] = c;
+    __syncthreads();
+    for (int o = 1; o < kRsThreads; o <<= 1) {
+        const unsigned v = t >= o ? tsum[t - o] : 0u;
         __syncthreads();
-        const int incl = carry + warp_sums[w] + x;
-        if (p < n_in) {
-            const int sid = incl - 1;
+        tsum[t] += v;
+        __syncthreads();
+    }
+    unsigned run = boff[blockIdx.x] + (t ? tsum[t - 1] : 0u);
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        const int p = base + j;
+        if (p < n) {
+            run += f[j];
+            const int sid = (int)run - 1;
             seg_id[p] = sid;
-            if (flag) {
+            if (f[j]) {
                 occ_vox[sid] = (int)(keys[p] >> 24);
                 seg_start[sid] = p;
             }
         }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = incl;
-        __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        *n_occ = carry;
-        seg_start[carry] = n_in;
-    }
+    if (blockIdx.x == 0 && t == 0) seg_start[counts[1]] = n;
 }
 
-hipError_t launch_segments(const unsigned long long *keys, int n_in, int *seg_id, int *occ_vox,
-                           int *seg_start, int *n_occ, hipStream_t st)
+hipError_t launch_segments(const unsigned long long *keys, int n_cap, int n, int *seg_id, int *occ_vox,
+                           int *seg_start, int *counts, unsigned *scratch, hipStream_t st)
 {
-    hipLaunchKernelGGL(segments_kernel, dim3(1), dim3(1024), 0, st, keys, n_in, seg_id, occ_vox,
-                       seg_start, n_occ);
+    const int nb = (max(n_cap, 1) + kRsTile - 1) / kRsTile;
+    hipLaunchKernelGGL(n_in_kernel, dim3(1), dim3(kRsThreads), 0, st, n, counts);
+    hipLaunchKernelGGL(seg_count_kernel, dim3(nb), dim3(kRsThreads), 0, st, keys, counts, scratch);
+    hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(1024), 0, st, scratch, nb, counts + 1);
+    hipLaunchKernelGGL(seg_write_kernel, dim3(nb), dim3(kRsThreads), 0, st, keys, counts, scratch, seg_id, occ_vox,
+                       seg_start);
     return hipGetLastError();
 }
 
 // FP32 path: occupied voxels re-ordered by z-line (i, j) then k, so that the
 // voxels of 64 consecutive z-lines form one contiguous range.  Keys are
-// ((line * nz + k) << 32) | (index in voxel order).
-__global__ void zline_keys_kernel(const int *__restrict__ occ_vox_v, int n_occ, int nxy, int nz,
-                                  unsigned long long *__restrict__ zkeys, int n_pad)
+// ((line * nz + k) << 32) | (index in voxel order).  The number of occupied
+// voxels is counts[1] (on the device), at most n_cap.
+__global__ void zline_keys_kernel(const int *__restrict__ occ_vox_v, const int *__restrict__ counts, int n_cap,
+                                  int nxy, int nz, unsigned long long *__restrict__ zkeys)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_pad) return;
-    if (p >= n_occ) {
-        zkeys[p] = ~0ull;
-        return;
-    }
+    if (p >= n_cap || p >= counts[1]) return;
     const int v = occ_vox_v[p];
     const unsigned long long line = (unsigned)(v % nxy), k = (unsigned)(v / nxy);
     zkeys[p] = ((line * (unsigned long long)nz + k) << 32) | (unsigned)p;
@@ -409,12 +518,13 @@ __global__ void zline_keys_kernel(const int *__restrict__ occ_vox_v, int n_occ, 
 // occupied voxel list in z order, and line_start[L] = first z-order entry of
 // z-line L (line_start[nxy] = n_occ).  Each entry fills the starts of the
 // lines between its predecessor's line and its own.
-__global__ void zline_scatter_kernel(const unsigned long long *__restrict__ zkeys, int n_occ, int nxy,
-                                     int nz, const int *__restrict__ occ_vox_v, int *__restrict__ occ_vox,
-                                     int *__restrict__ pos, int *__restrict__ line_start)
+__global__ void zline_scatter_kernel(const unsigned long long *__restrict__ zkeys, const int *__restrict__ counts,
+                                     int n_cap, int nxy, int nz, const int *__restrict__ occ_vox_v,
+                                     int *__restrict__ occ_vox, int *__restrict__ pos, int *__restrict__ line_start)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_occ) return;
+    const int n_occ = counts[1];
+    if (p >= n_cap || p >= n_occ) return;
     const unsigned long long key = zkeys[p];
     const int q = (int)(key & 0xffffffffull);
     pos[q] = p;
@@ -426,19 +536,29 @@ __global__ void zline_scatter_kernel(const unsigned long long *__restrict__ zkey
         for (int l = L + 1; l <= nxy; ++l) line_start[l] = n_occ;
 }
 
-hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
-                              unsigned long long *zkeys, int *occ_vox, int *pos, int *line_start,
-                              hipStream_t st)
+static int bit_length(unsigned long long x)
 {
-    if (n_occ <= 0) return hipSuccess;
-    int n_pad = 1;
-    while (n_pad < n_occ) n_pad <<= 1;
-    hipLaunchKernelGGL(zline_keys_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, st, occ_vox_v, n_occ,
-                       nxy, nz, zkeys, n_pad);
-    hipError_t e = launch_bitonic_sort(zkeys, n_pad, st);
+    int b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+hipError_t launch_zline_order(const int *occ_vox_v, const int *counts, int n_cap, int nxy, int nz,
+                              unsigned long long *zkeys, unsigned long long *zalt, unsigned *hist, int *occ_vox,
+                              int *pos, int *line_start, hipStream_t st)
+{
+    if (n_cap <= 0) return hipSuccess;
+    const dim3 grid((n_cap + 255) / 256), block(256);
+    hipLaunchKernelGGL(zline_keys_kernel, grid, block, 0, st, occ_vox_v, counts, n_cap, nxy, nz, zkeys);
+    // the z-line part of a key is below nxy * nz
+    hipError_t e = launch_radix_sort(zkeys, zalt, n_cap, counts + 1, 32,
+                                     bit_length((unsigned long long)nxy * (unsigned long long)nz), hist, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(zline_scatter_kernel, dim3((n_occ + 255) / 256), dim3(256), 0, st, zkeys, n_occ,
-                       nxy, nz, occ_vox_v, occ_vox, pos, line_start);
+    hipLaunchKernelGGL(zline_scatter_kernel, grid, block, 0, st, zkeys, counts, n_cap, nxy, nz, occ_vox_v, occ_vox,
+                       pos, line_start);
     return hipGetLastError();
 }
 
@@ -453,7 +573,7 @@ hipError_t launch_zline_order(const int *occ_vox_v, int n_occ, int nxy, int nz,
 // fast cells).  FP32 path: (P, R), applied as fmaf(rho, R, P); FP64 path: the
 // per-cell (a_i, b_i) in sorted order.
 __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
-                                  const int *__restrict__ seg_start, int n_occ, int ns,
+                                  const int *__restrict__ seg_start, const int *__restrict__ counts, int ns,
                                   const double *__restrict__ V, const double *__restrict__ S,
                                   const double *__restrict__ U, const double *__restrict__ RS,
                                   double dt, double vvox, const int *__restrict__ pos,
@@ -462,7 +582,7 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
                                   double *__restrict__ kcell, int *__restrict__ cell_of)
 {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (long long)n_occ * ns) return;
+    if (g >= (long long)counts[1] * ns) return;
     const int seg = (int)(g / ns), s = (int)(g % ns);
     const int out = pos ? pos[seg] : seg;
     double P = 0.0, R = 1.0;
@@ -484,28 +604,28 @@ __global__ void composites_kernel(const unsigned long long *__restrict__ keys,
     if (comp32_v) comp32_v[(size_t)s * v_stride + seg] = c32;  // substrate-major
 }
 
-hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, int n_occ, int ns,
-                             const double *V, const double *S, const double *U, const double *RS,
+hipError_t launch_composites(const unsigned long long *keys, const int *seg_start, const int *counts, int n_cap,
+                             int ns, const double *V, const double *S, const double *U, const double *RS,
                              double dt, double vvox, const int *pos, float2 *comp32, float2 *comp32_v,
                              int v_stride, double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st)
 {
-    const long long total = (long long)n_occ * ns;
+    const long long total = (long long)n_cap * ns;  // counts[1] * ns of them work
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(composites_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys,
-                       seg_start, n_occ, ns, V, S, U, RS, dt, vvox, pos, comp32, comp32_v, v_stride, ab64, krs,
+                       seg_start, counts, ns, V, S, U, RS, dt, vvox, pos, comp32, comp32_v, v_stride, ab64, krs,
                        kcell, cell_of);
     return hipGetLastError();
 }
 
 // First entry of every x-line (j + ny k) in the occupied voxels listed in
 // voxel order: the lower bound of the line's first voxel index.
-__global__ void xline_starts_kernel(const int *__restrict__ occ_vox_v, int n_occ, int nx, int nlines,
-                                    int *__restrict__ line_start)
+__global__ void xline_starts_kernel(const int *__restrict__ occ_vox_v, const int *__restrict__ counts, int nx,
+                                    int nlines, int *__restrict__ line_start)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l > nlines) return;
     const long long v0 = (long long)l * nx;
-    int lo = 0, hi = n_occ;
+    int lo = 0, hi = counts[1];
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if ((long long)occ_vox_v[mid] < v0)
@@ -516,11 +636,11 @@ __global__ void xline_starts_kernel(const int *__restrict__ occ_vox_v, int n_occ
     line_start[l] = lo;
 }
 
-hipError_t launch_xline_starts(const int *occ_vox_v, int n_occ, int nx, int nlines, int *line_start,
+hipError_t launch_xline_starts(const int *occ_vox_v, const int *counts, int nx, int nlines, int *line_start,
                                hipStream_t st)
 {
     if (nlines < 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(xline_starts_kernel, dim3((nlines + 1 + 255) / 256), dim3(256), 0, st, occ_vox_v, n_occ,
+    hipLaunchKernelGGL(xline_starts_kernel, dim3((nlines + 1 + 255) / 256), dim3(256), 0, st, occ_vox_v, counts,
                        nx, nlines, line_start);
     return hipGetLastError();
 }

@@ -52,13 +52,6 @@ int fail(int code, const std::string &msg)
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-int next_pow2(int n)
-{
-    int p = 1;
-    while (p < n) p <<= 1;
-    return p;
-}
-
 struct SimHost {
     int n[3] = {0, 0, 0};
     double h[3] = {0, 0, 0};
@@ -119,7 +112,6 @@ struct vl_ctx {
     int comp_total = 0;    // sum over sims of max_cells * ns
     int stage_cells = 0;   // max over sims of max_cells
     int stage_ns = 0;      // max over sims of ns
-    int key_pad = 0;       // next_pow2(stage_cells)
     int zl_total = 0;      // sum over sims with cells of (nx*ny + 1)
     int xs_total = 0;      // sum over sims eligible for carried sources of (ny*nz + 1)
     // cell sources: 0 separate kernel, 1 fused into the z sweep, 2 carried
@@ -154,11 +146,12 @@ struct vl_ctx {
 
     // workspace layout (byte offsets)
     size_t o_subs = 0, o_coef32 = 0, o_coefh = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0,
-           o_xl32 = 0;
+           o_xl32 = 0, o_xl64 = 0;
     size_t o_cells = 0, o_occ_prefix = 0, o_occ_vox = 0, o_seg_start = 0, o_comp = 0, o_ab = 0;
     size_t o_pos = 0, o_V = 0, o_S = 0, o_U = 0, o_RS = 0, o_keys = 0, o_seg_id = 0;
     size_t o_counters = 0, o_mass_part = 0, o_mass_out = 0, o_count = 0;
     size_t o_zkeys = 0, o_occ_tmp = 0, o_pos_idx = 0, o_line_start = 0;
+    size_t o_keys_alt = 0, o_zkeys_alt = 0, o_rs_hist = 0;
     size_t o_krs = 0, o_kcell = 0, o_cell_of = 0, o_occ_vox_v = 0;
     size_t o_xline_start = 0, o_comp_v = 0;
     size_t n_coef32 = 0, n_coef64 = 0;
@@ -353,8 +346,15 @@ int enqueue_step(vl_ctx *ctx, int phase)
                 return timed(ctx, VL_K_SWEEP_XY,
                              [&] { return vl::launch_sweep_xy(d, L.lds, subs, coef, field, st); });
             }
+            // a z launch streams its rows (non-temporal) unless one of its
+            // volumes applies cell sources after its stores in this step
+            bool nt = L.axis == 2;
+            for (int i = 0; nt && src.enabled && i < L.count; ++i) {
+                const SimHost &sh = ctx->sims[ctx->subs[ctx->itable[L.ids_off + i]].sim];
+                if (sh.n_occ > 0 && !(phase != kStepWhole && sh.xs_base >= 0)) nt = false;
+            }
             return timed(ctx, VL_K_SWEEP_X + L.axis, [&] {
-                return vl::launch_sweep_f32(L.axis, L.cap_idx, d, subs, coef, field, nullptr, src, st);
+                return vl::launch_sweep_f32(L.axis, L.cap_idx, d, subs, coef, field, nullptr, src, nt, st);
             });
         };
         for (int axis = 0; axis < 3; ++axis) {
@@ -366,7 +366,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
                                       ctx->at<int>(ctx->o_itable) + L.prefix_off, L.count, L.total_tiles,
                                       ctx->xcd_order ? 1 : 0};
                     rc = timed(ctx, VL_K_SWEEP_X, [&] {
-                        return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<float>(ctx->o_xl32),
+                        return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<double>(ctx->o_xl64),
                                                    field, nullptr, carry, st);
                     });
                     if (rc) return rc;
@@ -932,7 +932,6 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
         ctx->stage_cells = std::max(ctx->stage_cells, s.max_cells);
         ctx->stage_ns = std::max(ctx->stage_ns, s.ns);
     }
-    ctx->key_pad = next_pow2(std::max(ctx->stage_cells, 1));
 
     // workspace layout
     size_t w = 0;
@@ -946,6 +945,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_coefh = take(ctx->precision == VL_F32 ? sizeof(double2) * ctx->n_coef32 : 0);
     ctx->o_coef64 = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->n_coef64 : 0);
     ctx->o_xl32 = take(ctx->precision == VL_F32 ? sizeof(float) * ctx->n_xl32 : 0);
+    ctx->o_xl64 = take(ctx->precision == VL_F32 ? sizeof(double) * ctx->n_xl32 : 0);
     ctx->o_itable = take(sizeof(int) * ctx->itable.size());
     ctx->o_lltable = take(sizeof(long long) * ctx->lltable.size());
     ctx->o_faces = take(sizeof(int4) * ctx->faces.size());
@@ -967,14 +967,17 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->o_S = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
     ctx->o_U = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
     ctx->o_RS = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
-    ctx->o_keys = take(sizeof(unsigned long long) * ctx->key_pad);
+    ctx->o_keys = take(sizeof(unsigned long long) * ctx->stage_cells);
+    ctx->o_keys_alt = take(sizeof(unsigned long long) * ctx->stage_cells);
+    ctx->o_rs_hist = take(sizeof(unsigned) * (size_t)vl::radix_hist_entries(ctx->stage_cells));
     ctx->o_seg_id = take(sizeof(int) * ctx->stage_cells);
-    ctx->o_counters = take(sizeof(int) * 4);
+    ctx->o_counters = take(sizeof(int) * 8);
     ctx->o_mass_part = take(sizeof(double) * vl::kMassBlocks);
     ctx->o_mass_out = take(sizeof(double) * ctx->max_ns);
     ctx->o_count = take(sizeof(unsigned long long));
     const bool zorder = ctx->precision == VL_F32;
-    ctx->o_zkeys = take(zorder ? sizeof(unsigned long long) * ctx->key_pad : 0);
+    ctx->o_zkeys = take(zorder ? sizeof(unsigned long long) * ctx->stage_cells : 0);
+    ctx->o_zkeys_alt = take(zorder ? sizeof(unsigned long long) * ctx->stage_cells : 0);
     ctx->o_occ_tmp = take(zorder ? sizeof(int) * (ctx->stage_cells + 1) : 0);
     ctx->o_pos_idx = take(zorder ? sizeof(int) * ctx->stage_cells : 0);
     ctx->o_line_start = take(sizeof(int) * ctx->zl_total);
@@ -1019,7 +1022,7 @@ int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
                                    ctx->at<SubDev>(ctx->o_subs), st));
     if (ctx->precision == VL_F32)
         VL_HIP(vl::launch_xl_tables(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(), nullptr,
-                                    ctx->at<float>(ctx->o_xl32), st));
+                                    ctx->at<float>(ctx->o_xl32), ctx->at<double>(ctx->o_xl64), st));
     if (ctx->zl_total > 0)
         VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_line_start, 0, sizeof(int) * ctx->zl_total, st));
     VL_HIP(hipMemsetAsync(ctx->ws + ctx->o_qcounters, 0, sizeof(unsigned) * (2 + 3 * ctx->subs.size()), st));
@@ -1065,7 +1068,7 @@ int vl_update_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D, const
                                    ctx->at<SubDev>(ctx->o_subs), st));
     if (ctx->precision == VL_F32)
         VL_HIP(vl::launch_xl_tables(ctx->at<SubDev>(ctx->o_subs), (int)ctx->subs.size(), nullptr,
-                                    ctx->at<float>(ctx->o_xl32), st));
+                                    ctx->at<float>(ctx->o_xl32), ctx->at<double>(ctx->o_xl64), st));
     // the host copy of the descriptors must outlive the asynchronous upload
     VL_HIP(hipStreamSynchronize(st));
     return VL_OK;
@@ -1229,51 +1232,54 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_S, S, sizeof(double) * n * ns, kind, st));
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_U, U, sizeof(double) * n * ns, kind, st));
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_RS, rho_star, sizeof(double) * n * ns, kind, st));
+    // Binning on the device, its counts kept there (no host round trip
+    // between the kernels): keys, stable radix sort by voxel, occupied-voxel
+    // segments, the z-line order (FP32) and x-line starts, composites.  One
+    // read of the counts at the end.
     int *counters = ctx->at<int>(ctx->o_counters);
-    VL_HIP(hipMemsetAsync(counters, 0, sizeof(int) * 4, st));
-    const int n_pad = next_pow2(n);
+    unsigned *hist = ctx->at<unsigned>(ctx->o_rs_hist);
+    VL_HIP(vl::launch_upload_counts(counters, n, st));
     unsigned long long *keys = ctx->at<unsigned long long>(ctx->o_keys);
     VL_HIP(vl::launch_cell_keys(ctx->at<double>(ctx->o_pos), n, s.n[0], s.n[1], s.n[2], s.lo[0], s.lo[1],
-                                s.lo[2], s.h[0], s.h[1], s.h[2], keys, n_pad, counters, st));
-    VL_HIP(vl::launch_bitonic_sort(keys, n_pad, st));
-    int host_counters[4] = {0, 0, 0, 0};
-    VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+                                s.lo[2], s.h[0], s.h[1], s.h[2], keys, counters, st));
+    // voxel indices lie below n_vox, and the out-of-domain key (all ones) above
+    int vbits = 0;
+    for (unsigned long long x = (unsigned long long)s.n[0] * s.n[1] * s.n[2]; x; x >>= 1) ++vbits;
+    VL_HIP(vl::launch_radix_sort(keys, ctx->at<unsigned long long>(ctx->o_keys_alt), n, counters + 4, 24, vbits,
+                                 hist, st));
+    // FP32: occupied voxels first in voxel order (temporary), then re-ordered
+    // by z-line for the sources fused into the z sweep.
+    const bool zorder = ctx->precision == VL_F32;
+    int *occ_v = zorder ? ctx->at<int>(ctx->o_occ_vox_v) + s.occ_base : ctx->at<int>(ctx->o_occ_vox) + s.occ_base;
+    VL_HIP(vl::launch_segments(keys, n, n, ctx->at<int>(ctx->o_seg_id), occ_v,
+                               ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters, hist, st));
+    int *pos_idx = nullptr;
+    if (zorder) {
+        pos_idx = ctx->at<int>(ctx->o_pos_idx);
+        VL_HIP(vl::launch_zline_order(occ_v, counters, n, s.n[0] * s.n[1], s.n[2],
+                                      ctx->at<unsigned long long>(ctx->o_zkeys),
+                                      ctx->at<unsigned long long>(ctx->o_zkeys_alt), hist,
+                                      ctx->at<int>(ctx->o_occ_vox) + s.occ_base, pos_idx,
+                                      ctx->at<int>(ctx->o_line_start) + s.zl_base, st));
+        if (s.xs_base >= 0)
+            VL_HIP(vl::launch_xline_starts(occ_v, counters, s.n[0], s.n[1] * s.n[2],
+                                           ctx->at<int>(ctx->o_xline_start) + s.xs_base, st));
+    }
+    const double vvox = s.h[0] * s.h[1] * s.h[2];
+    VL_HIP(vl::launch_composites(keys, ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters, n, s.ns,
+                                 ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S), ctx->at<double>(ctx->o_U),
+                                 ctx->at<double>(ctx->o_RS), ctx->dt, vvox, pos_idx,
+                                 zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
+                                 zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr, s.max_cells,
+                                 ctx->at<double2>(ctx->o_ab) + s.ab_base,
+                                 zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
+                                 zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
+                                 zorder ? ctx->at<int>(ctx->o_cell_of) + s.occ_base : nullptr, st));
+    int host_counters[2] = {0, 0};
+    VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
     VL_HIP(hipStreamSynchronize(st));
     const int n_out = host_counters[0];
-    const int n_in = n - n_out;
-    int n_occ = 0;
-    if (n_in > 0) {
-        // FP32: occupied voxels first in voxel order (temporary), then
-        // re-ordered by z-line for the sources fused into the z sweep.
-        const bool zorder = ctx->precision == VL_F32;
-        int *occ_v = zorder ? ctx->at<int>(ctx->o_occ_vox_v) + s.occ_base : ctx->at<int>(ctx->o_occ_vox) + s.occ_base;
-        VL_HIP(vl::launch_segments(keys, n_in, ctx->at<int>(ctx->o_seg_id), occ_v,
-                                   ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters + 1, st));
-        VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
-        VL_HIP(hipStreamSynchronize(st));
-        n_occ = host_counters[1];
-        int *pos = nullptr;
-        if (zorder) {
-            pos = ctx->at<int>(ctx->o_pos_idx);
-            VL_HIP(vl::launch_zline_order(occ_v, n_occ, s.n[0] * s.n[1], s.n[2],
-                                          ctx->at<unsigned long long>(ctx->o_zkeys),
-                                          ctx->at<int>(ctx->o_occ_vox) + s.occ_base, pos,
-                                          ctx->at<int>(ctx->o_line_start) + s.zl_base, st));
-            if (s.xs_base >= 0)
-                VL_HIP(vl::launch_xline_starts(occ_v, n_occ, s.n[0], s.n[1] * s.n[2],
-                                               ctx->at<int>(ctx->o_xline_start) + s.xs_base, st));
-        }
-        const double vvox = s.h[0] * s.h[1] * s.h[2];
-        VL_HIP(vl::launch_composites(keys, ctx->at<int>(ctx->o_seg_start) + s.occ_base, n_occ, s.ns,
-                                     ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S),
-                                     ctx->at<double>(ctx->o_U), ctx->at<double>(ctx->o_RS), ctx->dt, vvox,
-                                     pos, zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
-                                     zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr, s.max_cells,
-                                     ctx->at<double2>(ctx->o_ab) + s.ab_base,
-                                     zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
-                                     zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
-                                     zorder ? ctx->at<int>(ctx->o_cell_of) + s.occ_base : nullptr, st));
-    }
+    const int n_occ = host_counters[1];
     s.n_occ = n_occ;
     s.n_out = n_out;
     if (n_out_of_domain) *n_out_of_domain = n_out;
@@ -1760,7 +1766,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
         if (o.second) {
             if (int rc = timed(ctx, VL_K_REPLAY_X, [&] {
                     const vl::CarriedSources none{nullptr, nullptr, nullptr, nullptr, 0};
-                    return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<float>(ctx->o_xl32), field,
+                    return vl::launch_sweep_xl(L.cap_idx, ctx->xl_lpw, d, subs, ctx->at<double>(ctx->o_xl64), field,
                                                (float *)(aws + A.raw[0]), none, st);
                 }))
                 return rc;
@@ -1768,7 +1774,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
         }
         if (int rc = timed(ctx, VL_K_REPLAY_X + axis, [&] {
                 return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
-                                            nosrc, st);
+                                            nosrc, axis == 2, st);
             }))
             return rc;
     }

@@ -34,7 +34,8 @@ __device__ __forceinline__ double xl_bdiag(int n, int row, double c, double sg)
     return (row == 0 || row == n - 1) ? 1.0 + c + sg : 1.0 + 2.0 * c + sg;
 }
 
-__global__ void __launch_bounds__(64) xl_tables_kernel(const SubDev *__restrict__ subs, float *__restrict__ xl32)
+__global__ void __launch_bounds__(64) xl_tables_kernel(const SubDev *__restrict__ subs, float *__restrict__ xl32,
+                                                       double *__restrict__ xl64)
 {
     __shared__ double sa[64], sb[64], sc[64];
     __shared__ double alf[64], ber[64];  // first al, first be of each lane's interval
@@ -47,6 +48,7 @@ __global__ void __launch_bounds__(64) xl_tables_kernel(const SubDev *__restrict_
     const int P = (n + K - 1) / K;
     const double c = S.c[0], sg = S.sigma;
     float *T = xl32 + S.xlane;
+    double *T64 = xl64 + S.xlane;
     const int nf = xl_fields(K);
     const bool act = l < P;
     const int s0 = K * l;
@@ -105,15 +107,23 @@ __global__ void __launch_bounds__(64) xl_tables_kernel(const SubDev *__restrict_
         }
         T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + l] = (m > 0) ? (float)c : 0.f;   // cprev
         T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + l] = (mn > 0) ? (float)c : 0.f;  // cnext
+        T64[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + l] = (m > 0) ? c : 0.0;
+        T64[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + l] = (mn > 0) ? c : 0.0;
     } else {
         T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + l] = 0.f;
         T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + l] = 0.f;
+        T64[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + l] = 0.0;
+        T64[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + l] = 0.0;
     }
     for (int t = 0; t < K - 1; ++t) {
         T[(0 * (K - 1) + t) * 64 + l] = (float)inv[t];
         T[(1 * (K - 1) + t) * 64 + l] = (float)ee[t];
         T[(2 * (K - 1) + t) * 64 + l] = (float)al[t];
         T[(3 * (K - 1) + t) * 64 + l] = (float)be[t];
+        T64[(0 * (K - 1) + t) * 64 + l] = inv[t];
+        T64[(1 * (K - 1) + t) * 64 + l] = ee[t];
+        T64[(2 * (K - 1) + t) * 64 + l] = al[t];
+        T64[(3 * (K - 1) + t) * 64 + l] = be[t];
     }
     // parallel cyclic reduction: level v eliminates the couplings at distance 2^v
     sa[l] = A;
@@ -141,16 +151,19 @@ __global__ void __launch_bounds__(64) xl_tables_kernel(const SubDev *__restrict_
         sc[l] = nc;
         T[(4 * (K - 1) + 2 * v) * 64 + l] = (float)k1;
         T[(4 * (K - 1) + 2 * v + 1) * 64 + l] = (float)k2;
+        T64[(4 * (K - 1) + 2 * v) * 64 + l] = k1;
+        T64[(4 * (K - 1) + 2 * v + 1) * 64 + l] = k2;
         __syncthreads();
     }
     T[(4 * (K - 1) + 2 * kXLaneLevels) * 64 + l] = act ? (float)(1.0 / sb[l]) : 0.f;
+    T64[(4 * (K - 1) + 2 * kXLaneLevels) * 64 + l] = act ? 1.0 / sb[l] : 0.0;
     (void)nf;
 }
 
-hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *, float *xl32, hipStream_t st)
+hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *, float *xl32, double *xl64, hipStream_t st)
 {
-    if (nsubs <= 0 || !xl32) return hipSuccess;
-    hipLaunchKernelGGL(xl_tables_kernel, dim3(nsubs), dim3(64), 0, st, subs, xl32);
+    if (nsubs <= 0 || !xl32 || !xl64) return hipSuccess;
+    hipLaunchKernelGGL(xl_tables_kernel, dim3(nsubs), dim3(64), 0, st, subs, xl32, xl64);
     return hipGetLastError();
 }
 
@@ -211,13 +224,15 @@ constexpr int kXlAhead = 2;
 
 template <int K, bool CARRY>
 __global__ void __launch_bounds__(256)
-sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *__restrict__ xl32,
+sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const double *__restrict__ xl64,
          float *__restrict__ field, float *__restrict__ raw, CarriedSources carry)
 {
     // per wave: which of a lane's voxels receive a carried source, and the
     // composites by voxel of the line
     __shared__ unsigned cs_mask[4][CARRY ? 64 : 1];
     __shared__ float2 cs_ab[4][CARRY ? 64 * K : 1];
+    // the volume's interval tables (FP64), field-major, one column per lane
+    __shared__ double xl_int[K > 1 ? 4 * (K - 1) * 64 : 1];
     constexpr int KM = K > 1 ? K - 1 : 1;
     const int parts = (kTileLines / 4) / lpw;  // workgroups per tile
     const int blk = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -238,26 +253,34 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     const int dmask = S.dir_mask;
     const int lo_f = (dmask & 1) ? 0 : -1;
     const int hi_f = (dmask & 2) ? 1 : -1;
-    const float fdec = (float)S.fdec;
+    const double fdec = S.fdec;
 
-    // this lane's table entries
-    const float *__restrict__ T = xl32 + S.xlane;
-    float inv[KM], ee[KM], al[KM], be[KM], k1[kXLaneLevels], k2[kXLaneLevels];
-#pragma unroll
-    for (int t = 0; t < KM; ++t) {
-        inv[t] = K > 1 ? T[(0 * (K - 1) + t) * 64 + lane] : 0.f;
-        ee[t] = K > 1 ? T[(1 * (K - 1) + t) * 64 + lane] : 0.f;
-        al[t] = K > 1 ? T[(2 * (K - 1) + t) * 64 + lane] : 0.f;
-        be[t] = K > 1 ? T[(3 * (K - 1) + t) * 64 + lane] : 0.f;
-    }
+    // The solve's arithmetic is FP64 (tables included); only the line's
+    // values and the interval results it keeps between phases are FP32:
+    // rounding inside FP32 recurrences is coherent across neighbouring lines
+    // and steps and accumulates like a bias.  The interval tables (4(K-1)
+    // FP64 values per lane) live in LDS, read per line, which keeps the
+    // kernel at four waves per SIMD; the reduction's multipliers stay in
+    // registers.
+    const double *__restrict__ T = xl64 + S.xlane;
+    for (int e = threadIdx.x; e < 4 * (K - 1) * 64; e += 256) xl_int[e] = T[e];
+    __syncthreads();
+    // Read at each use: the column index carries a per-line term that is
+    // zero (line indices stay below 2^28) but that the compiler cannot prove
+    // zero, so the reads are not hoisted out of the line loop into registers.
+    auto inv = [&](int tl, int t) { return K > 1 ? xl_int[(0 * (K - 1) + t) * 64 + tl] : 0.0; };
+    auto ee = [&](int tl, int t) { return K > 1 ? xl_int[(1 * (K - 1) + t) * 64 + tl] : 0.0; };
+    auto al = [&](int tl, int t) { return K > 1 ? xl_int[(2 * (K - 1) + t) * 64 + tl] : 0.0; };
+    auto be = [&](int tl, int t) { return K > 1 ? xl_int[(3 * (K - 1) + t) * 64 + tl] : 0.0; };
+    double k1[kXLaneLevels], k2[kXLaneLevels];
 #pragma unroll
     for (int v = 0; v < kXLaneLevels; ++v) {
         k1[v] = T[(4 * (K - 1) + 2 * v) * 64 + lane];
         k2[v] = T[(4 * (K - 1) + 2 * v + 1) * 64 + lane];
     }
-    const float binv = T[(4 * (K - 1) + 2 * kXLaneLevels) * 64 + lane];
-    const float cprev = T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + lane];
-    const float cnext = T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + lane];
+    const double binv = T[(4 * (K - 1) + 2 * kXLaneLevels) * 64 + lane];
+    const double cprev = T[(4 * (K - 1) + 2 * kXLaneLevels + 1) * 64 + lane];
+    const double cnext = T[(4 * (K - 1) + 2 * kXLaneLevels + 2) * 64 + lane];
 
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(field + S.base, S.vol);
     const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw ? raw + S.base : field + S.base, S.vol);
@@ -296,6 +319,12 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     }
     auto from_lane = [](int addr, float x) {
         return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+    };
+    auto from_lane_d = [](int addr, double x) {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
+        const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
     };
     // cell sources of the previous step carried into this solve (uniform):
     // each x-line's range [e0, e1) of the voxel-ordered occupied voxels, the
@@ -371,27 +400,29 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
                           vl_u32x2 rg, int vox0, float2 ab0) {
         constexpr bool FULL = decltype(full_c)::value;
         const int mm = FULL ? K - 1 : m;
+        const int tl = lane + ((row >> 30) << 6);  // the table column: lane
         if (decltype(carry_c)::value) carry_in(row, r, rg, vox0, ab0);
         // Dirichlet projection before the solve: the end voxels of the line
         r[0] = set_in_lo ? v_in_lo : r[0];
 #pragma unroll
         for (int t = 0; t < K; ++t) r[t] = (set_in_hi && t == mm) ? v_in_hi : r[t];
 
-        // the lane's interval: u = T_int^-1 r_int
+        // the lane's interval: u = T_int^-1 r_int (FP64 recurrences; the
+        // eliminated values and u are kept in FP32)
         float u[KM];
         {
             float y[KM];
-            float prev = 0.f;
+            double prev = 0.0;
 #pragma unroll
             for (int t = 0; t < K - 1; ++t) {
-                prev = fmaf(ee[t], prev, r[t] * inv[t]);
-                y[t] = t < mm ? prev : 0.f;
+                prev = fma(ee(tl, t), prev, (double)r[t] * inv(tl, t));
+                y[t] = t < mm ? (float)prev : 0.f;
             }
-            float nxt = 0.f;
+            double nxt = 0.0;
 #pragma unroll
             for (int t = K - 2; t >= 0; --t) {
-                nxt = t < mm ? fmaf(ee[t], nxt, y[t]) : 0.f;
-                u[t] = nxt;
+                nxt = t < mm ? fma(ee(tl, t), nxt, (double)y[t]) : 0.0;
+                u[t] = (float)nxt;
             }
             if (K == 1) u[0] = 0.f;
         }
@@ -404,24 +435,25 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
         for (int t = 0; t < K - 1; ++t)
             if (t == mm - 1) ulast = u[t];
         const float ufirst_next = from_lane(a_dn[0], u[0]);
-        float d = act ? fmaf(cnext, ufirst_next, fmaf(cprev, ulast, rsep)) : 0.f;
+        double d = act ? fma(cnext, (double)ufirst_next, fma(cprev, (double)ulast, (double)rsep)) : 0.0;
         // parallel cyclic reduction over the lanes (a level whose distance
         // reaches past the last lane has zero multipliers)
 #pragma unroll
         for (int v = 0; v < kXLaneLevels; ++v) {
-            const float dl = from_lane(a_up[v], d);
-            const float dr = from_lane(a_dn[v], d);
-            d = fmaf(-k2[v], dr, fmaf(-k1[v], dl, d));
+            const double dl = from_lane_d(a_up[v], d);
+            const double dr = from_lane_d(a_dn[v], d);
+            d = fma(-k2[v], dr, fma(-k1[v], dl, d));
         }
-        const float xs = d * binv;
-        const float xl = from_lane(a_up[0], xs);
+        const double xs = d * binv;
+        const double xl = from_lane_d(a_up[0], xs);
         // the lane's voxels; decay once per step after the x solve
         float o[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-            const float xi = (t < K - 1 && t < mm) ? fmaf(be[t < KM ? t : 0], xs, fmaf(al[t < KM ? t : 0], xl, u[t < KM ? t : 0]))
-                                                   : xs;
-            o[t] = xi * fdec;
+            const double xi = (t < K - 1 && t < mm)
+                                  ? fma(be(tl, t < KM ? t : 0), xs, fma(al(tl, t < KM ? t : 0), xl, (double)u[t < KM ? t : 0]))
+                                  : xs;
+            o[t] = (float)(xi * fdec);
         }
         const unsigned voff = line_off(row, true);
         if (raw) {  // uniform
@@ -516,7 +548,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const float *_
     else run(std::false_type{}, std::false_type{});
 }
 
-hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const float *xl32,
+hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *subs, const double *xl64,
                            float *field, float *raw, const CarriedSources &carry, hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;
@@ -528,9 +560,9 @@ hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *s
 #define VL_XL_CASE(k)                                                                                  \
     case k:                                                                                            \
         if (carry.enabled)                                                                             \
-            hipLaunchKernelGGL((sweep_xl<k, true>), grid, block, 0, st, L, lpw, subs, xl32, field, raw, carry); \
+            hipLaunchKernelGGL((sweep_xl<k, true>), grid, block, 0, st, L, lpw, subs, xl64, field, raw, carry); \
         else                                                                                           \
-            hipLaunchKernelGGL((sweep_xl<k, false>), grid, block, 0, st, L, lpw, subs, xl32, field, raw, carry); \
+            hipLaunchKernelGGL((sweep_xl<k, false>), grid, block, 0, st, L, lpw, subs, xl64, field, raw, carry); \
         break;
         VL_XL_CASE(1)
         VL_XL_CASE(2)

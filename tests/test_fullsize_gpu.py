@@ -12,7 +12,8 @@ names (``subset``) while the GPU runs the whole configuration.
 
   * single large simulation, 200^3 x 4, 1e5 cells: 100 steps, every substrate,
     once tuned and once with the lanes-along-the-line x solve and the sources
-    carried into the next x solve forced;
+    carried into the next x solve forced; and its full 1000 steps on the
+    substrates with the smallest and the largest D;
   * tumour scale, 400^3 x 8, 1e6 cells: 100 steps, the substrates with the
     smallest and the largest D and the one with the largest lambda;
   * the batch of 256 ragged simulations x 2: 200 steps, every simulation
@@ -100,6 +101,18 @@ def test_single_large_100_steps_every_substrate(single_large, forced):
     if force:
         assert opts["x_lanes"] == 1 and opts["sources"] == 2
     check(got.astype(np.float64), want, f"200^3x4 {forced}")
+
+
+def test_single_large_1000_steps(single_large):
+    """The configuration's own run length: 1000 steps of 200^3 x 4, checked on
+    the substrates with the smallest and the largest D (the oracle on those
+    two only; substrates do not interact)."""
+    spec, _ = single_large
+    (got,), _ = run_bench_shape([spec], 1000)
+    for s in (int(np.argmin(spec.D)), int(np.argmax(spec.D))):
+        print(f"200^3x4 1000 steps: substrate {s}, D {spec.D[s]:.4g}, lambda {spec.lam[s]:.4g}", flush=True)
+        want = run_oracle(subset(spec, [s]), 1000)
+        check(got[s:s + 1].astype(np.float64), want, f"200^3x4 1000 steps substrate {s}")
 
 
 # --------------------------------------------------------------------------
