@@ -278,12 +278,12 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * sources inside the z sweep, right after each tile's stores (the occupied
  * voxels of 64 z-lines form one contiguous range of a per-simulation list
  * ordered by z-line); 0 applies them with a separate kernel over all occupied
- * voxels; 2 carries a step's sources into the next step's x solve for the
- * simulations whose x-lines are solved with the lanes along the line (each
+ * voxels; 2 carries a step's sources into the next step's x solve (each
  * line gets them as it is loaded, before the Dirichlet projection that opens
- * the step), the others as with 1, and one pass at the end of every vl_step
- * call applies the last step's, so the field is whole whenever vl_step
- * returns.  All three give bitwise identical fields; vl_tune times them. */
+ * the step; both kinds of x solve do this), and one pass at the end of every
+ * vl_step call applies the last step's, so the field is whole whenever
+ * vl_step returns (with x and y solved per z-plane, 2 acts as 1).  All three
+ * give bitwise identical fields; vl_tune times them. */
 #define VL_OPT_FUSE_SOURCES 1
 /* VL_OPT_STEP_MODE (FP32 path): VL_MODE_LAUNCHES (default) launches one
  * kernel per sweep and capacity class, each covering every simulation;

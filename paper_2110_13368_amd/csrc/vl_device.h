@@ -175,9 +175,18 @@ struct XWide {
 // columns n-1 downwards).  For CAP >= 64 every needed chunk starts at a
 // column >= 0 and ends at <= n-1, so only the top wave's unneeded groups past
 // n-4 are clamped.
-template <int CAP>
+// Position in the stage of row q's column c of the chunk (0 <= c < 64).
+__device__ __forceinline__ int x_wide_slot(int q, int c)
+{
+    return (q >> 2) * kXBlk + (q & 3) * 64 + 4 * (((c >> 2) + 4 * (q & 3)) & 15) + (c & 3);
+}
+
+// on_chunk(c, cbase) runs once per chunk after the chunk has landed in the
+// stage and before it is read back (the cell sources carried into the x
+// solve are applied there).
+template <int CAP, typename F>
 __device__ __forceinline__ void x_load_wide(float (&v)[CAP], __amdgpu_buffer_rsrc_t rs, float *stw, bool top,
-                                            int n, int nel, int row_b, int xrows_left, int lane)
+                                            int n, int nel, int row_b, int xrows_left, int lane, F &&on_chunk)
 {
     constexpr int kChunks = (CAP + 63) / 64;
     const int rb = lane >> 4;
@@ -196,6 +205,7 @@ __device__ __forceinline__ void x_load_wide(float (&v)[CAP], __amdgpu_buffer_rsr
                     min(4 * k + rb, xrows_left - 1) * row_b + col * 4, 0, 0, 0);
             __builtin_amdgcn_s_waitcnt(0);
             wave_sync_lds();
+            on_chunk(c, cbase);
 #pragma unroll
             for (int h = 0; h < 16; ++h) {
                 if (c * 64 + 4 * h < CAP && c * 64 + 4 * h < nel) {

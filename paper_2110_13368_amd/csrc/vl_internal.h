@@ -167,13 +167,15 @@ hipError_t launch_sweep_xl(int K, int lpw, const SweepLaunch &L, const SubDev *s
                            float *raw, const CarriedSources &carry, hipStream_t st);
 
 // a3-a5, FP32 split-Thomas sweeps along axis (0, 1, 2) for capacity class cap_idx.
+// carry (x only): the previous step's cell sources applied to the staged lines.
 // raw (may be null, same layout as the field) receives each solve's output
 // before the Dirichlet projection, for the adjoint's replay.  nontemporal (z
 // only): stream the rows with non-temporal loads and stores, for launches
 // none of whose tiles applies cell sources after its stores.
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L,
                             const SubDev *subs, const double2 *coef, float *field, float *raw,
-                            const FusedSources &src, bool nontemporal, hipStream_t st);
+                            const FusedSources &src, const CarriedSources &carry, bool nontemporal,
+                            hipStream_t st);
 
 // a9: adjoint sweep along axis, in place on w (same layout as the field).  The
 // Dirichlet adjoint (zero at Dirichlet voxels) is applied on load and store;

@@ -284,7 +284,7 @@ bool z_skipped(const vl_ctx *ctx, int q, int axis)
 // simulations into the next step's x solve (VL_OPT_FUSE_SOURCES 2).
 bool carries(const vl_ctx *ctx)
 {
-    if (ctx->precision != VL_F32 || ctx->fuse_sources != 2 || !ctx->x_lanes) return false;
+    if (ctx->precision != VL_F32 || ctx->fuse_sources != 2) return false;
     if (ctx->step_mode != VL_MODE_LAUNCHES || (ctx->fuse_xy && ctx->xy_ready)) return false;
     for (const SimHost &s : ctx->sims)
         if (s.xs_base >= 0 && s.n_occ > 0) return true;
@@ -354,7 +354,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
                 if (sh.n_occ > 0 && !(phase != kStepWhole && sh.xs_base >= 0)) nt = false;
             }
             return timed(ctx, VL_K_SWEEP_X + L.axis, [&] {
-                return vl::launch_sweep_f32(L.axis, L.cap_idx, d, subs, coef, field, nullptr, src, nt, st);
+                return vl::launch_sweep_f32(L.axis, L.cap_idx, d, subs, coef, field, nullptr, src, carry, nt, st);
             });
         };
         for (int axis = 0; axis < 3; ++axis) {
@@ -921,11 +921,9 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
         if (s.max_cells > 0 && ctx->precision == VL_F32) {
             s.zl_base = ctx->zl_total;
             ctx->zl_total += s.n[0] * s.n[1] + 1;
-            // sources can ride on the x solve with lanes along the line
-            if (s.n[0] >= vl::kXLaneMinN && s.n[0] <= 64 * vl::kXLaneMaxK) {
-                s.xs_base = ctx->xs_total;
-                ctx->xs_total += s.n[1] * s.n[2] + 1;
-            }
+            // sources can ride on the next step's x solve (either kind)
+            s.xs_base = ctx->xs_total;
+            ctx->xs_total += s.n[1] * s.n[2] + 1;
         }
         ctx->cap_total += s.max_cells + 1;
         ctx->comp_total += s.max_cells * s.ns;
@@ -1773,8 +1771,9 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
             continue;
         }
         if (int rc = timed(ctx, VL_K_REPLAY_X + axis, [&] {
+                const vl::CarriedSources none{nullptr, nullptr, nullptr, nullptr, 0};
                 return vl::launch_sweep_f32(axis, L.cap_idx, d, subs, coef, field, (float *)(aws + A.raw[axis]),
-                                            nosrc, axis == 2, st);
+                                            nosrc, none, axis == 2, st);
             }))
             return rc;
     }

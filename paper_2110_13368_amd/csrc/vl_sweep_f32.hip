@@ -40,7 +40,8 @@ namespace vl {
 template <int AXIS, int CAP, bool XSTAGE, bool NT = false>
 __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const double2 *__restrict__ coef,
                                            float *__restrict__ field, float *__restrict__ raw,
-                                           const FusedSources &src, FwdLds<CAP, XSTAGE> &sh)
+                                           const FusedSources &src, const CarriedSources &carry,
+                                           FwdLds<CAP, XSTAGE> &sh)
 {
     constexpr int kW = XStage<CAP>::W;    // stage columns per chunk
     constexpr int kSX = XStage<CAP>::SX;  // stage row stride
@@ -81,7 +82,9 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     unsigned lane_b = 0;     // per-lane byte offset (y, z: along x; x: row start)
     int row_b = 0;           // bytes between rows (y, z) / between x-lines (x)
     int xrows_left = 0;      // x-lines of the tile that exist
-    bool line_ok = true;     // this lane's line exists (x: not a clamped copy)
+    bool line_ok = true;     // this lane's line exists (x: not a clamped copy; a copy's
+                             // values differ once carried sources are applied, so it
+                             // must not store)
     if (AXIS == 0) {
         const int nrows = ny * nz;
         const int r0 = local * kTileLines;
@@ -120,6 +123,41 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     }
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(field + base, S.base + S.vol - base);
     const int wface = top_face(dmask & on);  // whole line Dirichlet
+
+    // x: cell sources of the previous step carried into this solve (as in the
+    // x solve with lanes along the line): the occupied voxels of the tile's
+    // x-lines form one range of the simulation's voxel-ordered list, each
+    // applied (rho R + P, the update of every other placement) to the staged
+    // line values before the Dirichlet projection that opens the step
+    const SimCells *CC = (AXIS == 0 && carry.enabled) ? &carry.cells[S.sim] : nullptr;
+    const bool carried = CC != nullptr && CC->xs_base >= 0;  // uniform
+    const int *__restrict__ c_xs = carried ? carry.xline_start + CC->xs_base : nullptr;
+    const int *__restrict__ c_vox = carried ? carry.occ_vox_v + CC->occ_base : nullptr;
+    const float2 *__restrict__ c_ab =
+        carried ? carry.comp_v + CC->comp_base + (size_t)S.sub * CC->occ_cap : nullptr;
+    const int c_r0 = local * kTileLines;
+    const int c_e0 = carried ? c_xs[c_r0] : 0;
+    const int c_e1 = carried ? c_xs[min(c_r0 + kTileLines, S.n[1] * S.n[2])] : 0;
+    // the entries whose columns this wave holds in [cs, cs + width) of the
+    // stage, 64 at a time; slot(q, c) is row q's column cs + c in the stage
+    auto carry_chunk = [&](int cs, int width, auto slot) {
+        if (!carried) return;
+        for (int eb = c_e0; eb < c_e1; eb += kWave) {  // uniform
+            const int e = eb + lane;
+            if (e < c_e1) {
+                const int vox = c_vox[e];
+                const int q = vox / nx - c_r0;
+                const int i = vox - (q + c_r0) * nx;
+                const bool own = top ? i < m : i > m;
+                if (own && i >= cs && i < cs + width) {
+                    float *pq = slot(q, i - cs);
+                    const float2 ab = c_ab[e];
+                    *pq = fmaf(*pq, ab.y, ab.x);
+                }
+            }
+        }
+        wave_sync_lds();
+    };
     const int lo_f = (dmask >> (2 * AXIS)) & 1 ? 2 * AXIS : -1;
     const int hi_f = (dmask >> (2 * AXIS + 1)) & 1 ? 2 * AXIS + 1 : -1;
     const int f_first = max(wface, max(lo_f, n == 1 ? hi_f : -1));  // row 0
@@ -129,7 +167,10 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
 
     // ---- load the half line (local t: wave 0 row t, wave 1 row n-1-t) ----
     if (AXIS == 0 && XWide<CAP>::value) {
-        x_load_wide<CAP>(v, rs, stage + wave * 64 * kSX, top, n, nel, row_b, xrows_left, lane);
+        float *stw = stage + wave * 64 * kSX;
+        x_load_wide<CAP>(v, rs, stw, top, n, nel, row_b, xrows_left, lane, [&](int, int cbase) {
+            carry_chunk(cbase, 64, [&](int q, int c) { return stw + x_wide_slot(q, c); });
+        });
     } else if (AXIS == 0) {
         float *st = stage + wave * 64 * kSX;
 #pragma unroll
@@ -151,6 +192,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
                 }
                 __builtin_amdgcn_s_waitcnt(0);
                 wave_sync_lds();
+                carry_chunk(cs, kW, [&](int q, int cc) { return st + q * kSX + cc; });
                 if (top) {
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
@@ -207,6 +249,20 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
         float rm;
         if (AXIS == 0) {
             rm = bload(rs, lane_b + (unsigned)m * 4u, 0);
+            if (carried && line_ok) {  // the middle column's source, if any, from this lane's own x-line
+                const int r = c_r0 + lane;
+                const int want = r * nx + m;
+                for (int e = c_xs[r]; e < c_xs[r + 1]; ++e) {
+                    const int vox = c_vox[e];
+                    if (vox >= want) {
+                        if (vox == want) {
+                            const float2 ab = c_ab[e];
+                            rm = fmaf(rm, ab.y, ab.x);
+                        }
+                        break;
+                    }
+                }
+            }
             if (m == 0) {
                 const int f0 = max(lo_f, n == 1 ? hi_f : -1);
                 if (f0 >= 0) rm = S.dval32[f0];
@@ -232,12 +288,12 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     if (raw != nullptr) {
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(raw + base, S.base + S.vol - base);
         if (AXIS == 0 && XWide<CAP>::value) {
-            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm32);
+            if (top && line_ok) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm32);
             x_store_wide<CAP>(v, rr, stage + wave * 64 * kSX, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
         } else if (AXIS == 0) {
             // through the LDS stage, like the field store below
             float *st = stage + wave * 64 * kSX;
-            if (top) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm32);
+            if (top && line_ok) bstore(rr, lane_b + (unsigned)m * 4u, 0, xm32);
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
                 if (c * kW < nel) {
@@ -292,11 +348,11 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
 
     // ---- store ----
     if (AXIS == 0 && XWide<CAP>::value) {
-        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
+        if (top && line_ok) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
         x_store_wide<CAP>(v, rs, stage + wave * 64 * kSX, top, n, nel, row_b, xrows_left, lane, lane_b, line_ok);
     } else if (AXIS == 0) {
         float *st = stage + wave * 64 * kSX;
-        if (top) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
+        if (top && line_ok) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             if (c * kW < nel) {
@@ -355,13 +411,13 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
 template <int AXIS, int CAP, bool NT>
 __global__ void __launch_bounds__(128)
 sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const double2 *__restrict__ coef,
-          float *__restrict__ field, float *__restrict__ raw, FusedSources src)
+          float *__restrict__ field, float *__restrict__ raw, FusedSources src, CarriedSources carry)
 {
     __shared__ FwdLds<CAP, AXIS == 0> sh;
     const int tile = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int slot = find_slot(L.tile_prefix, L.count, tile);
     const int local = tile - L.tile_prefix[slot];
-    sweep_tile<AXIS, CAP, AXIS == 0, NT>(subs[L.sub_ids[slot]], local, coef, field, raw, src, sh);
+    sweep_tile<AXIS, CAP, AXIS == 0, NT>(subs[L.sub_ids[slot]], local, coef, field, raw, src, carry, sh);
 }
 
 // The whole step in one launch.  Workgroups take tiles from one queue in the
@@ -379,6 +435,7 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const double
 {
     __shared__ FwdLds<CAP, true> sh;
     __shared__ int s_tile;
+    const CarriedSources nocarry{nullptr, nullptr, nullptr, nullptr, 0};
     unsigned *head = Q.counters;
     unsigned *exited = Q.counters + 1;
     unsigned *done = Q.counters + 2;  // [phase][slot]
@@ -420,11 +477,11 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const double
         }
         const SubDev &S = subs[Q.sub_ids[slot]];
         if (phase == 0)
-            sweep_tile<0, CAP, true>(S, local, coef, field, nullptr, src, sh);
+            sweep_tile<0, CAP, true>(S, local, coef, field, nullptr, src, nocarry, sh);
         else if (phase == 1)
-            sweep_tile<1, CAP, true>(S, local, coef, field, nullptr, src, sh);
+            sweep_tile<1, CAP, true>(S, local, coef, field, nullptr, src, nocarry, sh);
         else
-            sweep_tile<2, CAP, true>(S, local, coef, field, nullptr, src, sh);
+            sweep_tile<2, CAP, true>(S, local, coef, field, nullptr, src, nocarry, sh);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
@@ -444,13 +501,15 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const double
 
 template <int AXIS, bool NT>
 static hipError_t launch_axis(int cap_idx, const SweepLaunch &L, const SubDev *subs, const double2 *coef,
-                              float *field, float *raw, const FusedSources &src, hipStream_t st)
+                              float *field, float *raw, const FusedSources &src, const CarriedSources &carry,
+                              hipStream_t st)
 {
     const dim3 grid(L.total_tiles), block(128);
     switch (cap_idx) {
 #define VL_CAP_CASE(i)                                                                                            \
     case i:                                                                                                       \
-        hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[i], NT>), grid, block, 0, st, L, subs, coef, field, raw, src); \
+        hipLaunchKernelGGL((sweep_f32<AXIS, kCaps[i], NT>), grid, block, 0, st, L, subs, coef, field, raw, src,  \
+                           carry);                                                                                \
         break;
         VL_CAP_CASE(0)
         VL_CAP_CASE(1)
@@ -503,14 +562,15 @@ hipError_t persistent_blocks_per_cu(int cap_idx, int *blocks)
 
 hipError_t launch_sweep_f32(int axis, int cap_idx, const SweepLaunch &L, const SubDev *subs,
                             const double2 *coef, float *field, float *raw, const FusedSources &src,
-                            bool nontemporal, hipStream_t st)
+                            const CarriedSources &carry, bool nontemporal, hipStream_t st)
 {
     if (L.total_tiles <= 0) return hipSuccess;
-    if (axis == 0) return launch_axis<0, false>(cap_idx, L, subs, coef, field, raw, src, st);
-    if (axis == 1) return launch_axis<1, false>(cap_idx, L, subs, coef, field, raw, src, st);
+    const CarriedSources none{nullptr, nullptr, nullptr, nullptr, 0};
+    if (axis == 0) return launch_axis<0, false>(cap_idx, L, subs, coef, field, raw, src, carry, st);
+    if (axis == 1) return launch_axis<1, false>(cap_idx, L, subs, coef, field, raw, src, none, st);
     if (axis == 2)
-        return nontemporal ? launch_axis<2, true>(cap_idx, L, subs, coef, field, raw, src, st)
-                           : launch_axis<2, false>(cap_idx, L, subs, coef, field, raw, src, st);
+        return nontemporal ? launch_axis<2, true>(cap_idx, L, subs, coef, field, raw, src, none, st)
+                           : launch_axis<2, false>(cap_idx, L, subs, coef, field, raw, src, none, st);
     return hipErrorInvalidValue;
 }
 

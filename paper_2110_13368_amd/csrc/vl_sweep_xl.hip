@@ -231,8 +231,9 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const double *
     // composites by voxel of the line
     __shared__ unsigned cs_mask[4][CARRY ? 64 : 1];
     __shared__ float2 cs_ab[4][CARRY ? 64 * K : 1];
-    // the volume's interval tables (FP64), field-major, one column per lane
-    __shared__ double xl_int[K > 1 ? 4 * (K - 1) * 64 : 1];
+    // the volume's interval tables (FP64), field-major, three columns: lane
+    // 0, the middle lanes, the last active lane
+    __shared__ double xl_int[K > 1 ? 4 * (K - 1) * 3 : 1];
     constexpr int KM = K > 1 ? K - 1 : 1;
     const int parts = (kTileLines / 4) / lpw;  // workgroups per tile
     const int blk = L.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -261,17 +262,25 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const double *
     // and steps and accumulates like a bias.  The interval tables (4(K-1)
     // FP64 values per lane) live in LDS, read per line, which keeps the
     // kernel at four waves per SIMD; the reduction's multipliers stay in
-    // registers.
+    // registers.  Lanes 1 .. P-2 each hold an interval of K-1 inner rows of
+    // the line, so their tables are equal; only lane 0 (whose interval starts
+    // at the line's first row) and lane P-1 (whose interval is shorter when n
+    // is not a multiple of K) differ.  So LDS keeps three columns and every
+    // table read is a near-broadcast (three addresses per wave).
     const double *__restrict__ T = xl64 + S.xlane;
-    for (int e = threadIdx.x; e < 4 * (K - 1) * 64; e += 256) xl_int[e] = T[e];
+    for (int e = threadIdx.x; e < 4 * (K - 1) * 3; e += 256) {
+        const int col = e % 3;
+        xl_int[e] = T[(e / 3) * 64 + (col == 0 ? 0 : col == 1 ? min(1, P - 1) : P - 1)];
+    }
     __syncthreads();
+    const int tcol = lane == 0 ? 0 : (lane < P - 1 ? 1 : 2);
     // Read at each use: the column index carries a per-line term that is
     // zero (line indices stay below 2^28) but that the compiler cannot prove
     // zero, so the reads are not hoisted out of the line loop into registers.
-    auto inv = [&](int tl, int t) { return K > 1 ? xl_int[(0 * (K - 1) + t) * 64 + tl] : 0.0; };
-    auto ee = [&](int tl, int t) { return K > 1 ? xl_int[(1 * (K - 1) + t) * 64 + tl] : 0.0; };
-    auto al = [&](int tl, int t) { return K > 1 ? xl_int[(2 * (K - 1) + t) * 64 + tl] : 0.0; };
-    auto be = [&](int tl, int t) { return K > 1 ? xl_int[(3 * (K - 1) + t) * 64 + tl] : 0.0; };
+    auto inv = [&](int tl, int t) { return K > 1 ? xl_int[(0 * (K - 1) + t) * 3 + tl] : 0.0; };
+    auto ee = [&](int tl, int t) { return K > 1 ? xl_int[(1 * (K - 1) + t) * 3 + tl] : 0.0; };
+    auto al = [&](int tl, int t) { return K > 1 ? xl_int[(2 * (K - 1) + t) * 3 + tl] : 0.0; };
+    auto be = [&](int tl, int t) { return K > 1 ? xl_int[(3 * (K - 1) + t) * 3 + tl] : 0.0; };
     double k1[kXLaneLevels], k2[kXLaneLevels];
 #pragma unroll
     for (int v = 0; v < kXLaneLevels; ++v) {
@@ -400,7 +409,7 @@ sweep_xl(SweepLaunch L, int lpw, const SubDev *__restrict__ subs, const double *
                           vl_u32x2 rg, int vox0, float2 ab0) {
         constexpr bool FULL = decltype(full_c)::value;
         const int mm = FULL ? K - 1 : m;
-        const int tl = lane + ((row >> 30) << 6);  // the table column: lane
+        const int tl = tcol + ((row >> 30) << 2);  // the table column
         if (decltype(carry_c)::value) carry_in(row, r, rg, vox0, ab0);
         // Dirichlet projection before the solve: the end voxels of the line
         r[0] = set_in_lo ? v_in_lo : r[0];

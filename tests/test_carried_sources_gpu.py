@@ -49,19 +49,23 @@ def _line_cells(spec, lines, seed):
 
 
 def _batch():
-    # eligible (x-lines of 129+ voxels, cells), eligible without cells, not
-    # eligible (short x-lines), and one with x-lines holding more than 64
-    # occupied voxels
+    # x-lines of 129+ voxels with cells, the same without cells, short x-lines
+    # (the split x solve carries them, its 32-column stage for lines of up to
+    # 65 voxels), lines with more than 64 occupied voxels, and lines of 322+
+    # voxels (the split solve's 16-byte stage when the lanes solve is off);
+    # cells on the middle column of the split solve included
     a = _spec((150, 9, 7), 2, "mixed", 400, 1, layout="gaussian")
     b = _spec((131, 5, 4), 1, "dirichlet", 0, 2)
     c = _spec((60, 17, 11), 2, "mixed", 300, 3)
     d = _line_cells(_spec((200, 6, 5), 3, "neumann", 100, 4), [(2, 3, 200), (0, 0, 70), (5, 4, 64), (1, 2, 65)], 41)
     e = _spec((257, 3, 4), 1, "mixed", 200, 5)
-    return [a, b, c, d, e]
+    f = _line_cells(_spec((97, 8, 6), 2, "mixed", 150, 6), [(3, 2, 97), (0, 5, 40)], 61)
+    g = _line_cells(_spec((333, 4, 3), 2, "dirichlet", 100, 7), [(1, 1, 333), (3, 2, 90)], 71)
+    return [a, b, c, d, e, f, g]
 
 
 @pytest.mark.parametrize("steps", [1, 2, 5])
-@pytest.mark.parametrize("x_lanes", [1, 2])
+@pytest.mark.parametrize("x_lanes", [0, 1, 2])
 def test_carried_sources_equal_other_modes(steps, x_lanes):
     specs = _batch()
     f2, n2 = run_gpu(specs, steps, x_lanes=x_lanes, sources_mode=2)
@@ -143,8 +147,6 @@ def test_hundreds_of_fast_cells_in_one_voxel(x_lanes):
     assert n == 550
     fields = {}
     for mode in (0, 1, 2):
-        if mode == 2 and not x_lanes:
-            continue
         (f,), n_out = run_gpu([spec], 6, x_lanes=x_lanes, sources_mode=mode)
         assert n_out == [0]
         assert np.all(np.isfinite(f))
