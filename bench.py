@@ -262,6 +262,32 @@ def adjoint_cpu_baseline(wl, grads, budget_s: float):
                       f"with {spec.cells.n} cells", "seconds": round(t, 3)}
 
 
+def apply_launch_options(ctx, args, vb):
+    """The launch configuration of an FP32 context: the tuner's choice on the
+    bound buffers (setup, not timed) unless --mode launches, then every option
+    given on the command line on top."""
+    if args.mode == "tuned":
+        ctx.tune(None)
+    else:
+        ctx.set_option(vb.VL_OPT_STEP_MODE,
+                       vb.VL_MODE_PERSISTENT if args.mode == "persistent" else vb.VL_MODE_LAUNCHES)
+    if args.x_lanes != "auto":
+        ctx.set_option(vb.VL_OPT_X_LANES, int(args.x_lanes))
+    if args.x_lane_lines != "auto":
+        ctx.set_option(vb.VL_OPT_X_LANE_LINES, int(args.x_lane_lines))
+    if args.sources != "auto":
+        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, int(args.sources))
+    if args.xy != "auto":
+        ctx.set_option(vb.VL_OPT_FUSE_XY, int(args.xy))
+
+
+def launch_config(ctx, vb) -> dict:
+    """The launch options a run used (what its kernel names follow from)."""
+    return {"x_lanes": ctx.get_option(vb.VL_OPT_X_LANES), "x_lines_per_wave": ctx.get_option(vb.VL_OPT_X_LANE_LINES),
+            "xy_per_plane": ctx.get_option(vb.VL_OPT_FUSE_XY), "sources": ctx.get_option(vb.VL_OPT_FUSE_SOURCES),
+            "xcd_order": ctx.get_option(vb.VL_OPT_XCD_ORDER)}
+
+
 def run_adjoint(args):
     """Reverse-mode gradient of the differentiation workload: one vl_adjoint
     call over --steps steps (default 200) with a checkpoint every 20 steps,
@@ -277,10 +303,11 @@ def run_adjoint(args):
     print(f"bench: adjoint of {wl.name}: {E} voxel-substrates, {n_steps} steps, checkpoint every {ckpt}",
           file=sys.stderr, flush=True)
     ctx = vb.Context(wl.sims)
-    ctx.tune(None)  # launch configuration of the forward steps and replays; setup, not timed
+    apply_launch_options(ctx, args, vb)  # tuned, then any option forced on the command line
     for k, s in enumerate(wl.sims):
         ctx.set_field(k, s.rho0)
     x_lanes_opt = ctx.get_option(vb.VL_OPT_X_LANES)
+    launch = launch_config(ctx, vb)
     rng = np.random.default_rng(211013368 + 40)
     grads = [rng.normal(size=s.field_shape) for s in wl.sims]
     g = ctx.to_field_layout([a.astype(np.float32) for a in grads])
@@ -340,7 +367,8 @@ def run_adjoint(args):
         "data": "synthetic (seeded generators shaped like the paper's tumour workloads)",
         "config": {"workload": wl.name, "voxel_substrates": E, "grid": list(wl.sims[0].shape),
                    "n_sub": wl.sims[0].n_sub, "cells": int(wl.sims[0].cells.n), "ckpt_every": ckpt,
-                   "parallelism": "single-gpu", "x_lanes_min_line": {0: None, 1: 129, 2: 65}[x_lanes_opt]},
+                   "parallelism": "single-gpu", "x_lanes_min_line": {0: None, 1: 129, 2: 65}[x_lanes_opt],
+                   "launch": launch},
         "gradients": {"dD": [float(x) for x in dD], "dlambda": [float(x) for x in dl]},
         "roofline": roofline, "kernels": kernels,
     }
@@ -372,6 +400,8 @@ def main():
                     help="also time the steps with a snapshot of the field to pinned host memory every N steps")
     ap.add_argument("--move-cells-every", type=int, default=0,
                     help="also time steps with the cells moved and re-binned on the device every N steps")
+    ap.add_argument("--xy", default="auto", choices=["auto", "0", "1"],
+                    help="force x and y solved per z-plane where planes fit in LDS (1) or not (0), after tuning")
     ap.add_argument("--sources", default="auto", choices=["auto", "0", "1", "2"],
                     help="force where cell sources are applied (after tuning): 0 own kernel, 1 in the z sweep, "
                          "2 carried into the next x solve")
@@ -404,17 +434,8 @@ def run_workload(args, config: str, cpu: bool, copy_ref: bool, fp64: bool = True
 
     precision = vb.VL_F64 if wl.dtype == "f64" else vb.VL_F32
     ctx = vb.Context(wl.sims, precision=precision)
-    if args.mode == "tuned":
-        ctx.tune(None)  # times the step modes on these buffers; setup, not timed
-    else:
-        ctx.set_option(vb.VL_OPT_STEP_MODE,
-                       vb.VL_MODE_PERSISTENT if args.mode == "persistent" else vb.VL_MODE_LAUNCHES)
-    if args.x_lanes != "auto" and precision == vb.VL_F32:
-        ctx.set_option(vb.VL_OPT_X_LANES, int(args.x_lanes))
-    if args.x_lane_lines != "auto" and precision == vb.VL_F32:
-        ctx.set_option(vb.VL_OPT_X_LANE_LINES, int(args.x_lane_lines))
-    if args.sources != "auto" and precision == vb.VL_F32:
-        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, int(args.sources))
+    if precision == vb.VL_F32:
+        apply_launch_options(ctx, args, vb)
     mode = "persistent" if ctx.get_option(vb.VL_OPT_STEP_MODE) == vb.VL_MODE_PERSISTENT else "launches"
     fuse_src = {0: "own kernel", 1: "in the z sweep", 2: "carried into the next x solve"}[
         ctx.get_option(vb.VL_OPT_FUSE_SOURCES)] if precision == vb.VL_F32 else "own kernel"

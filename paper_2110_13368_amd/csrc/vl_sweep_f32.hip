@@ -46,11 +46,12 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     constexpr int kW = XStage<CAP>::W;    // stage columns per chunk
     constexpr int kSX = XStage<CAP>::SX;  // stage row stride
     constexpr int kChunks = (CAP + kW - 1) / kW;
-    // NT (z launches whose tiles re-read no voxel after their stores): the
-    // rows lie a plane apart and each 256-byte row is read and written once,
-    // so the loads and stores are non-temporal (5 % faster on 400^3 x 8; y,
-    // whose rows are neighbours, was not faster, and a z tile that applies
-    // cell sources after its stores would lose those lines)
+    // NT (z launches of long lines whose tiles re-read no voxel after their
+    // stores): the rows lie a plane apart and each 256-byte row is read and
+    // written once, so the loads and stores are non-temporal (5 % faster on
+    // 400^3 x 8; y, whose rows are neighbours, was not faster, nor were
+    // shorter z-lines, and a z tile that applies cell sources after its
+    // stores would lose those lines)
     constexpr int kPol = NT ? kNonTemporal : 0;
     double(&xch)[2][kWave] = sh.xch;
     double2 *cs_lds = sh.piv;
