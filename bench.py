@@ -186,7 +186,8 @@ def kernel_profile(ctx, steps: int):
 def copy_reference(nbytes: int, reps: int = 20):
     """Device-to-device copies of nbytes: torch's elementwise copy and the
     library's copy probe (vl_copy_probe) with 4- and 16-byte accesses per
-    lane, ordinary or non-temporal loads and stores.  The fastest is the
+    lane, ordinary or non-temporal loads and stores, between two buffers and
+    in place.  The fastest is the
     practical bandwidth ceiling for a sweep (which reads and writes every
     element once); each is a kernel of known traffic (nbytes read, nbytes
     written per launch) that scales the FETCH_SIZE / WRITE_SIZE counters."""
@@ -211,6 +212,11 @@ def copy_reference(nbytes: int, reps: int = 20):
         for nt in (0, 3):
             probe[f"width{width}_nt{nt}"] = rate(
                 lambda: vb.vl_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, width, nt, stream))
+    # in place (source = destination), the way a sweep moves its field
+    for width in (4, 16):
+        for nt in (0, 3):
+            probe[f"in_place_width{width}_nt{nt}"] = rate(
+                lambda: vb.vl_copy_probe(dst.data_ptr(), dst.data_ptr(), nbytes, width, nt, stream))
     if not torch.equal(dst, src):
         raise RuntimeError("vl_copy_probe: destination differs from source")
     out["vl_copy_probe_GBps"] = probe

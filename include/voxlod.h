@@ -389,15 +389,18 @@ int vl_set_profiling(vl_ctx *ctx, int enable);
 int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms);
 
 /* Copy probe (measurement plumbing; no passage of the paper defines it):
- * copies bytes from src to dst, both device memory, 16-byte aligned, not
- * overlapping, bytes a multiple of 16, with width-byte accesses per lane (4,
+ * copies bytes from src to dst, both device memory, 16-byte aligned, either
+ * the same buffer (dst == src: every element read and written back in place,
+ * the way a sweep updates its field) or not overlapping at all, bytes a
+ * multiple of 16, with width-byte accesses per lane (4,
  * 8 or 16) and, per bit of nontemporal, non-temporal loads (bit 0) and
  * stores (bit 1), asynchronously on stream (hipStream_t as void*, NULL = the
  * null stream).  Each sweep of vl_step reads and writes every element once,
  * so a copy of the field's bytes is the practical ceiling a sweep is measured
  * against; it is also the kernel of known traffic that scales the HBM byte
- * counters.  The caller owns both buffers.  VL_E_ARG for a bad argument,
- * VL_E_HIP if the launch fails. */
+ * counters.  The caller owns both buffers.  VL_E_ARG for a bad argument
+ * (including buffers that overlap without being the same), VL_E_HIP if the
+ * launch fails. */
 int vl_copy_probe(void *dst, const void *src, size_t bytes, int width, int nontemporal, void *stream);
 
 /* For callers that cannot allocate device memory (code under stream capture,

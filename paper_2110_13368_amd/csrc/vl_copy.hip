@@ -3,8 +3,10 @@
 // once, so a copy of the same bytes is the fastest a sweep can be on this
 // memory system; the variants here (4-, 8- or 16-byte accesses per lane,
 // ordinary or non-temporal loads and stores) show which access shapes reach
-// it.  Also the kernel of known traffic (bytes read = bytes written = size)
-// that scales the HBM byte counters.
+// it.  With the destination equal to the source the buffer is rewritten in
+// place, which is how the sweeps move their field (each element read and
+// written back where it lies).  Also the kernel of known traffic (bytes read
+// = bytes written = size) that scales the HBM byte counters.
 #include "vl_internal.h"
 
 namespace vl {
@@ -40,6 +42,30 @@ copy_probe_kernel(const T *__restrict__ src, T *__restrict__ dst, size_t n)
     }
 }
 
+// In place: every element read and then written back unchanged by the same
+// thread (no restrict: source and destination are one buffer).
+template <typename T, bool NTL, bool NTS>
+__global__ void __launch_bounds__(kCopyThreads) rewrite_probe_kernel(T *buf, size_t n)
+{
+    const size_t base = (size_t)blockIdx.x * (kCopyThreads * kCopyUnroll) + threadIdx.x;
+    T r[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + (size_t)u * kCopyThreads;
+        if (i < n) r[u] = NTL ? __builtin_nontemporal_load(buf + i) : buf[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + (size_t)u * kCopyThreads;
+        if (i < n) {
+            if (NTS)
+                __builtin_nontemporal_store(r[u], buf + i);
+            else
+                buf[i] = r[u];
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_typed(const void *src, void *dst, size_t bytes, int nt, hipStream_t st)
 {
@@ -48,6 +74,15 @@ hipError_t launch_typed(const void *src, void *dst, size_t bytes, int nt, hipStr
     const dim3 grid((unsigned)((n + per - 1) / per)), block(kCopyThreads);
     const T *s = (const T *)src;
     T *d = (T *)dst;
+    if (src == dst) {
+        switch (nt & 3) {
+        case 0: hipLaunchKernelGGL((rewrite_probe_kernel<T, false, false>), grid, block, 0, st, d, n); break;
+        case 1: hipLaunchKernelGGL((rewrite_probe_kernel<T, true, false>), grid, block, 0, st, d, n); break;
+        case 2: hipLaunchKernelGGL((rewrite_probe_kernel<T, false, true>), grid, block, 0, st, d, n); break;
+        default: hipLaunchKernelGGL((rewrite_probe_kernel<T, true, true>), grid, block, 0, st, d, n); break;
+        }
+        return hipGetLastError();
+    }
     switch (nt & 3) {
     case 0: hipLaunchKernelGGL((copy_probe_kernel<T, false, false>), grid, block, 0, st, s, d, n); break;
     case 1: hipLaunchKernelGGL((copy_probe_kernel<T, true, false>), grid, block, 0, st, s, d, n); break;
@@ -60,7 +95,7 @@ hipError_t launch_typed(const void *src, void *dst, size_t bytes, int nt, hipStr
 }  // namespace
 
 // width: bytes per lane access (4, 8 or 16); nt: bit 0 non-temporal loads,
-// bit 1 non-temporal stores.  bytes is a multiple of 16 and below 2^32 *
+// bit 1 non-temporal stores; src == dst rewrites the buffer in place.  bytes is a multiple of 16 and below 2^32 *
 // (kCopyThreads * kCopyUnroll) * width (checked by the caller).
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, int width, int nt, hipStream_t st)
 {

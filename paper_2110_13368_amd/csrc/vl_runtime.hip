@@ -1911,7 +1911,7 @@ int vl_copy_probe(void *dst, const void *src, size_t bytes, int width, int nonte
     if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return fail(VL_E_ARG, "vl_copy_probe: buffers must be 16-byte aligned");
     if (bytes / (size_t)width / 1024u >= (1ull << 31)) return fail(VL_E_ARG, "vl_copy_probe: bytes too large");
     const char *a = (const char *)src, *b = (const char *)dst;
-    if (a < b + bytes && b < a + bytes) return fail(VL_E_ARG, "vl_copy_probe: buffers overlap");
+    if (a != b && a < b + bytes && b < a + bytes) return fail(VL_E_ARG, "vl_copy_probe: buffers overlap");
     VL_HIP(vl::launch_copy_probe(src, dst, bytes, width, nontemporal, (hipStream_t)stream));
     return VL_OK;
 }

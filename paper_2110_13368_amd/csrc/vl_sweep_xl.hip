@@ -171,7 +171,7 @@ hipError_t launch_xl_tables(const SubDev *subs, int nsubs, const float2 *, float
 // The sweep.  The launch covers tiles of 64 x-lines (the split sweep's
 // tiling); 16 / lpw workgroups of four waves share a tile, and each wave
 // solves lpw consecutive lines one after another, with the loads of the next
-// two lines issued before the current line is solved.  Fewer lines per wave
+// three lines issued before the current line is solved.  Fewer lines per wave
 // make more, shorter-lived workgroups (a shorter tail at the end of the
 // launch); more lines per wave hide more load latency within a wave.
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ void xl_store(const float (&o)[K], __amdgpu_buffer_rs
     }
 }
 
-constexpr int kXlAhead = 2;
+constexpr int kXlAhead = 3;
 
 template <int K, bool CARRY>
 __global__ void __launch_bounds__(256)

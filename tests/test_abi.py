@@ -161,6 +161,7 @@ def test_copy_probe_rejects_bad_arguments_on_the_host():
     assert _code(vb.vl_copy_probe, 4100, 8192, 1024) == vb.VL_E_ARG  # misaligned
     assert _code(vb.vl_copy_probe, 4096, 4608, 1024) == vb.VL_E_ARG  # overlapping
     assert "overlap" in vb.vl_last_error()
+    assert _code(vb.vl_copy_probe, 4096, 4080, 1024) == vb.VL_E_ARG  # overlapping, source above
 
 
 def test_mass_noalloc_rejects_bad_arguments_on_the_host():

@@ -21,3 +21,17 @@ def test_copy_probe_copies_exactly(width, nt, nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[:n], src[:n])
     assert bool((dst[n:] == 7).all())
+
+
+@pytest.mark.parametrize("width", [4, 16])
+@pytest.mark.parametrize("nt", [0, 3])
+def test_copy_probe_in_place_leaves_the_buffer_unchanged(width, nt):
+    import torch
+    nbytes = (1 << 20) + 16 * 37
+    n = nbytes // 4
+    buf = torch.randint(-2 ** 31, 2 ** 31 - 1, (n + 64,), dtype=torch.int32, device="cuda")
+    ref = buf.clone()
+    print(f"copy probe in place: width {width}, nt {nt}", flush=True)
+    vb.vl_copy_probe(buf.data_ptr(), buf.data_ptr(), nbytes, width, nt, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, ref)
