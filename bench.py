@@ -143,8 +143,10 @@ def time_moving_cells(ctx, wl, steps: int, every: int):
     """Steps with the cells of every simulation moved and re-binned from device
     arrays every `every` steps (vl_upload_cells_dev: voxel index, sort,
     composites; the positions are prepared on the device beforehand, a small
-    random walk per move).  Returns (seconds, uploads, host seconds in the
-    upload calls, which include waiting for the steps queued before them)."""
+    random walk per move; no count of cells off the grid is asked for, so an
+    upload waits for the stream only to check the arrays).  Returns (seconds,
+    uploads, host seconds in the upload calls, which include waiting for the
+    steps queued before them)."""
     import torch
     n_moves = max(steps // every, 1)
     g = torch.Generator(device=ctx.device).manual_seed(211013368 + 50)
@@ -163,7 +165,7 @@ def time_moving_cells(ctx, wl, steps: int, every: int):
     for m in range(n_moves):
         u0 = time.perf_counter()
         for k, (pos, V, S, U, rs) in enumerate(dev):
-            ctx.upload_cells_device(k, pos[m], V, S, U, rs)
+            ctx.upload_cells_device(k, pos[m], V, S, U, rs, count_out=False)
         t_up += time.perf_counter() - u0
         take = min(every, steps - done)
         ctx.step(take)
@@ -312,8 +314,6 @@ def run_adjoint(args):
     apply_launch_options(ctx, args, vb)  # tuned, then any option forced on the command line
     for k, s in enumerate(wl.sims):
         ctx.set_field(k, s.rho0)
-    x_lanes_opt = ctx.get_option(vb.VL_OPT_X_LANES)
-    launch = launch_config(ctx, vb)
     rng = np.random.default_rng(211013368 + 40)
     grads = [rng.normal(size=s.field_shape) for s in wl.sims]
     g = ctx.to_field_layout([a.astype(np.float32) for a in grads])
@@ -331,6 +331,32 @@ def run_adjoint(args):
         torch.cuda.synchronize()
         return vb.vl_adjoint(ctx.h, n, ckpt, ws.data_ptr(), g.data_ptr(), g0.data_ptr(), nvol,
                              dS.data_ptr(), dU.data_ptr())
+
+    # The tuner times forward steps, but the reverse x solve follows the
+    # forward's x option and is faster with lanes along the line.  Unless an
+    # option was given, the adjoint takes whichever of the tuner's choice and
+    # the lanes solve for lines of 65+ voxels (without per-plane x+y) reverses
+    # faster, each timed once after a warm-up call (setup, not timed).
+    if args.mode == "tuned" and all(getattr(args, a) == "auto" for a in ("x_lanes", "x_lane_lines", "sources", "xy")):
+        cands = [{vb.VL_OPT_X_LANES: ctx.get_option(vb.VL_OPT_X_LANES),
+                  vb.VL_OPT_FUSE_XY: ctx.get_option(vb.VL_OPT_FUSE_XY)},
+                 {vb.VL_OPT_X_LANES: 2, vb.VL_OPT_FUSE_XY: 0}]
+        best = None
+        for cand in cands:
+            for o, v in cand.items():
+                ctx.set_option(o, v)
+            call(n_steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            call(n_steps)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if best is None or t < best[0]:
+                best = (t, cand)
+        for o, v in best[1].items():
+            ctx.set_option(o, v)
+    x_lanes_opt = ctx.get_option(vb.VL_OPT_X_LANES)
+    launch = launch_config(ctx, vb)
 
     call(n_steps)  # allocates the workspace; warm-up
     for _ in range(max(args.warmup, 0) // 20):

@@ -243,10 +243,17 @@ int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double
  * steps: the agents' mechanics can update them on the device and the
  * re-binning (voxel index, sort, composites; the same kernels as above)
  * needs no host copy.  The arrays are checked on the device first (volumes
- * finite and > 0, rates finite and >= 0, targets finite); on a failed check
- * it returns VL_E_ARG and the previous cells stay.  Synchronises the stream.
- * Cells come from the moving agents of the paper's hybrid model (Eq. 1,
- * section "Future Work" on moving cell secretion/uptake to the device). */
+ * finite and > 0, rates finite and >= 0, targets finite), which waits for
+ * the stream once; on a failed check it returns VL_E_ARG and the previous
+ * cells stay.  With n_out_of_domain NULL nothing else waits: the binning is
+ * queued on the bound stream and reads the arrays there after the call
+ * returns, so the caller leaves them unchanged until the stream has passed
+ * the upload (the next vl_sync, or stream-ordered work); a non-null
+ * n_out_of_domain reads the count back and synchronises the stream.  The
+ * step graphs of vl_step survive uploads that keep every simulation's cell
+ * count.  Cells come from the moving agents of the paper's hybrid model
+ * (Eq. 1, section "Future Work" on moving cell secretion/uptake to the
+ * device). */
 int vl_upload_cells_dev(vl_ctx *ctx, int sim, int n, const double *pos, const double *V,
                         const double *S, const double *U, const double *rho_star,
                         int *n_out_of_domain);
@@ -258,7 +265,9 @@ int vl_upload_cells_dev(vl_ctx *ctx, int sim, int n, const double *pos, const do
  * (section "Future Work").  VL_E_STATE before vl_bind; n_steps < 0 is
  * VL_E_ARG.  Faults of the launched kernels surface at vl_sync.  With a
  * non-null stream the step is captured once into a hipGraph and replayed; the
- * graph is rebuilt after any change of cells or binding. */
+ * graph is rebuilt after a change of binding or options, or an upload that
+ * changes a simulation's number of cells (the cell tables themselves are
+ * read from the workspace at every replay). */
 int vl_step(vl_ctx *ctx, int n_steps);
 /* Wait for the work queued on the bound stream (plumbing).  VL_E_HIP carries
  * a kernel fault; VL_E_STATE reports a one-launch step whose tile gave up

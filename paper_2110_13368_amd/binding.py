@@ -205,15 +205,18 @@ def vl_snapshot_wait(ctx) -> None:
     _check(lib().vl_snapshot_wait(ctx), "vl_snapshot_wait")
 
 
-def vl_upload_cells_dev(ctx, sim, n: int, pos_ptr: int, V_ptr: int, S_ptr: int, U_ptr: int, rs_ptr: int) -> int:
+def vl_upload_cells_dev(ctx, sim, n: int, pos_ptr: int, V_ptr: int, S_ptr: int, U_ptr: int, rs_ptr: int,
+                        count_out: bool = True):
     """Cell upload from device arrays (raw pointers: pos n x 3, V n, S / U /
     rho_star n x n_sub, float64, contiguous); returns the cells outside the
-    grid."""
+    grid, or None with count_out=False (then the call does not wait for the
+    binning, which reads the arrays on the context's stream)."""
     n_out = C.c_int(0)
     _check(lib().vl_upload_cells_dev(ctx, int(sim), int(n), C.c_void_p(pos_ptr), C.c_void_p(V_ptr),
-                                     C.c_void_p(S_ptr), C.c_void_p(U_ptr), C.c_void_p(rs_ptr), C.byref(n_out)),
+                                     C.c_void_p(S_ptr), C.c_void_p(U_ptr), C.c_void_p(rs_ptr),
+                                     C.byref(n_out) if count_out else None),
            "vl_upload_cells_dev")
-    return n_out.value
+    return n_out.value if count_out else None
 
 
 def vl_upload_cells(ctx, sim, pos, V, S, U, rho_star, n_sub: int) -> int:
@@ -453,10 +456,14 @@ class Context:
         self._autograd_params = None
         return n_out
 
-    def upload_cells_device(self, k: int, pos, V, S, U, rho_star) -> int:
+    def upload_cells_device(self, k: int, pos, V, S, U, rho_star, count_out: bool = True):
         """Cells from torch tensors on this context's device (float64: pos
-        (n, 3), V (n,), S / U / rho_star (n, n_sub)); the tensors must stay
-        alive until the call returns (it synchronises)."""
+        (n, 3), V (n,), S / U / rho_star (n, n_sub)).  Returns the cells off
+        the grid (the call then waits for the binning), or None with
+        count_out=False: the binning is queued on the context's stream and
+        reads the tensors there, which this object keeps alive and marks as
+        used on that stream; the caller must not write them until the stream
+        has passed the upload (e.g. sync())."""
         torch = self.torch
         ts = [t.contiguous() for t in (pos, V, S, U, rho_star)]
         for t in ts:
@@ -467,7 +474,10 @@ class Context:
             raise ValueError("cell tensor shapes do not match")
         if self.stream is not None:  # the tensors were written on the caller's stream
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        n_out = vl_upload_cells_dev(self.h, k, n, *[t.data_ptr() for t in ts])
+        n_out = vl_upload_cells_dev(self.h, k, n, *[t.data_ptr() for t in ts], count_out=count_out)
+        if not count_out and self.stream is not None:
+            for t in ts:  # not handed to other allocations before the stream has read them
+                t.record_stream(self.stream)
         self.cells[k] = DeviceCells(*ts)
         self._autograd_params = None
         return n_out

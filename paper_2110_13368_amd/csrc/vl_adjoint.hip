@@ -311,7 +311,7 @@ __device__ __forceinline__ int find_slot_int(const int *__restrict__ prefix, int
 }
 
 __global__ void sources_adjoint_kernel(const SimCells *__restrict__ cells, int nsims,
-                                       const int *__restrict__ occ_prefix, int total_occ,
+                                       const int *__restrict__ occ_prefix, int occ_bound,
                                        const SubDev *__restrict__ subs, const int *__restrict__ occ_vox_v,
                                        const int *__restrict__ seg_start, const double2 *__restrict__ ab,
                                        const double *__restrict__ krs, const double *__restrict__ kcell,
@@ -321,7 +321,7 @@ __global__ void sources_adjoint_kernel(const SimCells *__restrict__ cells, int n
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
-    if (j >= total_occ) return;
+    if (j >= occ_bound || j >= occ_prefix[nsims]) return;  // past the occupied voxels
     const int sim = find_slot_int(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns) return;
@@ -349,15 +349,15 @@ __global__ void sources_adjoint_kernel(const SimCells *__restrict__ cells, int n
     w[at] = (float)wb;
 }
 
-hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
                                   int max_ns, const SubDev *subs, const int *occ_vox_v,
                                   const int *seg_start, const double2 *ab, const double *krs,
                                   const double *kcell, const int *cell_of, const float *rho, float *w,
                                   const int *cell_out_base, double *dS, double *dU, hipStream_t st)
 {
-    if (total_occ <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_adjoint_kernel, dim3((total_occ + 127) / 128, max_ns), dim3(128), 0, st, cells,
-                       nsims, occ_prefix, total_occ, subs, occ_vox_v, seg_start, ab, krs, kcell, cell_of, rho, w,
+    if (occ_bound <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_adjoint_kernel, dim3((occ_bound + 127) / 128, max_ns), dim3(128), 0, st, cells,
+                       nsims, occ_prefix, occ_bound, subs, occ_vox_v, seg_start, ab, krs, kcell, cell_of, rho, w,
                        cell_out_base, dS, dU);
     return hipGetLastError();
 }

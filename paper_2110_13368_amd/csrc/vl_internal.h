@@ -191,7 +191,7 @@ hipError_t launch_reduce_partials(const SweepLaunch &L, int axis, const double *
 // voxels walks back through each voxel's cells; dS, dU (per cell and
 // substrate, in upload order) accumulate.
 hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *occ_prefix,
-                                  int total_occ, int max_ns, const SubDev *subs,
+                                  int occ_bound, int max_ns, const SubDev *subs,
                                   const int *occ_vox_v, const int *seg_start,
                                   const double2 *ab, const double *krs, const double *kcell,
                                   const int *cell_of, const float *rho, float *w,
@@ -238,17 +238,21 @@ hipError_t launch_composites(const unsigned long long *keys, const int *seg_star
                              int v_stride, double2 *ab64, double *krs, double *kcell, int *cell_of, hipStream_t st);
 hipError_t launch_xline_starts(const int *occ_vox_v, const int *counts, int nx, int nlines, int *line_start,
                                hipStream_t st);
+// the upload's occupied-voxel count into the cell tables and the prefix over
+// the simulations (counts null: no cells)
+hipError_t launch_finish_upload(const int *counts, SimCells *cells, int sim, int nsims, int xs_base, int *occ_prefix,
+                                hipStream_t st);
 hipError_t launch_zline_order(const int *occ_vox_v, const int *counts, int n_cap, int nxy, int nz,
                               unsigned long long *zkeys, unsigned long long *zalt, unsigned *hist, int *occ_vox,
                               int *pos, int *line_start, hipStream_t st);
 
 // a5/a6: sources over the occupied voxels of every simulation.
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix,
-                              int total_occ, int max_ns, const SubDev *subs,
+                              int occ_bound, int max_ns, const SubDev *subs,
                               const int *occ_vox, const float2 *comp, float *field,
                               int only_carried, hipStream_t st);
 hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ_prefix,
-                                int total_occ, const SubDev *subs, const int *occ_vox,
+                                int occ_bound, const SubDev *subs, const int *occ_vox,
                                 const int *seg_start, const double2 *ab, double *field,
                                 hipStream_t st);
 

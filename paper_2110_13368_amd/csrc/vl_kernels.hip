@@ -617,6 +617,35 @@ hipError_t launch_composites(const unsigned long long *keys, const int *seg_star
     return hipGetLastError();
 }
 
+// The end of a simulation's upload, on the device so that the host need not
+// read the counts back: its occupied-voxel count (counts[1], none without
+// counts) into its entry of the cell tables, whether its sources can be
+// carried into the next x solve (only with occupied voxels), and the
+// exclusive prefix of the occupied voxels over the simulations, which the
+// sources kernels search and whose last entry bounds them.  One thread; the
+// kernels launched after it on the stream see the new tables.
+__global__ void finish_upload_kernel(const int *__restrict__ counts, SimCells *__restrict__ cells, int sim,
+                                     int nsims, int xs_base, int *__restrict__ occ_prefix)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int n_occ = counts ? counts[1] : 0;
+    cells[sim].n_occ = n_occ;
+    cells[sim].xs_base = n_occ > 0 ? xs_base : -1;
+    int acc = 0;
+    occ_prefix[0] = 0;
+    for (int k = 0; k < nsims; ++k) {
+        acc += cells[k].n_occ;
+        occ_prefix[k + 1] = acc;
+    }
+}
+
+hipError_t launch_finish_upload(const int *counts, SimCells *cells, int sim, int nsims, int xs_base, int *occ_prefix,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(finish_upload_kernel, dim3(1), dim3(64), 0, st, counts, cells, sim, nsims, xs_base, occ_prefix);
+    return hipGetLastError();
+}
+
 // First entry of every x-line (j + ny k) in the occupied voxels listed in
 // voxel order: the lower bound of the line's first voxel index.
 __global__ void xline_starts_kernel(const int *__restrict__ occ_vox_v, const int *__restrict__ counts, int nx,
@@ -676,13 +705,13 @@ __device__ __forceinline__ void apply_composite(const SimCells &C, int jl, int s
 
 // FP32: one thread per (occupied voxel, substrate).
 __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims,
-                                   const int *__restrict__ occ_prefix, int total_occ,
+                                   const int *__restrict__ occ_prefix, int occ_bound,
                                    const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
                                    const float2 *__restrict__ comp, float *__restrict__ field, int only_carried)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
-    if (j >= total_occ) return;
+    if (j >= occ_bound || j >= occ_prefix[nsims]) return;  // past the occupied voxels
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns || (only_carried && C.xs_base < 0)) return;
@@ -695,49 +724,49 @@ __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims
 // stores (which already hold the last Dirichlet projection).  skip_carried:
 // leave those whose sources the next x solve applies.
 __global__ void sources_thin_f32_kernel(const SimCells *__restrict__ cells, int nsims,
-                                        const int *__restrict__ occ_prefix, int total_occ,
+                                        const int *__restrict__ occ_prefix, int occ_bound,
                                         const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
                                         const float2 *__restrict__ comp, float *__restrict__ field, int skip_carried)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
-    if (j >= total_occ) return;
+    if (j >= occ_bound || j >= occ_prefix[nsims]) return;  // past the occupied voxels
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns || subs[C.sub0].n[2] != 1 || (skip_carried && C.xs_base >= 0)) return;
     apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox, comp, field);
 }
 
-hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
                                    int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
                                    float *field, int skip_carried, hipStream_t st)
 {
-    if (total_occ <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_thin_f32_kernel, dim3((total_occ + 255) / 256, max_ns), dim3(256), 0, st,
-                       cells, nsims, occ_prefix, total_occ, subs, occ_vox, comp, field, skip_carried);
+    if (occ_bound <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_thin_f32_kernel, dim3((occ_bound + 255) / 256, max_ns), dim3(256), 0, st,
+                       cells, nsims, occ_prefix, occ_bound, subs, occ_vox, comp, field, skip_carried);
     return hipGetLastError();
 }
 
-hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
                               int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
                               float *field, int only_carried, hipStream_t st)
 {
-    if (total_occ <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_f32_kernel, dim3((total_occ + 255) / 256, max_ns), dim3(256), 0, st,
-                       cells, nsims, occ_prefix, total_occ, subs, occ_vox, comp, field, only_carried);
+    if (occ_bound <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_f32_kernel, dim3((occ_bound + 255) / 256, max_ns), dim3(256), 0, st,
+                       cells, nsims, occ_prefix, occ_bound, subs, occ_vox, comp, field, only_carried);
     return hipGetLastError();
 }
 
 // FP64 plain path: one thread per occupied voxel, cells applied one after
 // another in upload order: rho <- (rho + a_i) / b_i.
 __global__ void sources_plain_kernel(const SimCells *__restrict__ cells, int nsims,
-                                     const int *__restrict__ occ_prefix, int total_occ,
+                                     const int *__restrict__ occ_prefix, int occ_bound,
                                      const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
                                      const int *__restrict__ seg_start, const double2 *__restrict__ ab,
                                      double *__restrict__ field)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= total_occ) return;
+    if (j >= occ_bound || j >= occ_prefix[nsims]) return;  // past the occupied voxels
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     const int jl = j - occ_prefix[sim];
@@ -754,13 +783,13 @@ __global__ void sources_plain_kernel(const SimCells *__restrict__ cells, int nsi
     }
 }
 
-hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
                                 const SubDev *subs, const int *occ_vox, const int *seg_start,
                                 const double2 *ab, double *field, hipStream_t st)
 {
-    if (total_occ <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_plain_kernel, dim3((total_occ + 255) / 256), dim3(256), 0, st, cells,
-                       nsims, occ_prefix, total_occ, subs, occ_vox, seg_start, ab, field);
+    if (occ_bound <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sources_plain_kernel, dim3((occ_bound + 255) / 256), dim3(256), 0, st, cells,
+                       nsims, occ_prefix, occ_bound, subs, occ_vox, seg_start, ab, field);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include "voxlod.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,7 +21,7 @@ hipError_t launch_check_cells(int n, int ns, const double *V, const double *S, c
                               int *bad, hipStream_t st);
 // cell sources of the simulations one voxel thick, whose z solve is not
 // launched (vl_kernels.hip)
-hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int total_occ,
+hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
                                    int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
                                    float *field, int skip_carried, hipStream_t st);
 // the adjoint's reverse x solve with the lanes along the line (vl_adjoint_xl.hip)
@@ -69,7 +70,9 @@ struct SimHost {
     // cell tables
     int occ_base = 0, comp_base = 0, ab_base = 0, zl_base = -1;
     int xs_base = -1;  // x-line starts of the carried sources, -1 when not eligible
-    int n_cells = 0, n_occ = 0, n_out = 0;
+    int n_cells = 0;        // cells of the last upload
+    int n_occ = 0, n_out = 0;  // its occupied voxels and cells off the grid, as last read back (the
+                               // device's cell tables hold the occupied count of every upload)
     long long nvox() const { return (long long)n[0] * n[1] * n[2]; }
 };
 
@@ -287,8 +290,28 @@ bool carries(const vl_ctx *ctx)
     if (ctx->precision != VL_F32 || ctx->fuse_sources != 2) return false;
     if (ctx->step_mode != VL_MODE_LAUNCHES || (ctx->fuse_xy && ctx->xy_ready)) return false;
     for (const SimHost &s : ctx->sims)
-        if (s.xs_base >= 0 && s.n_occ > 0) return true;
+        if (s.xs_base >= 0 && s.n_cells > 0) return true;
     return false;
+}
+
+// The host knows how many cells each simulation holds but not, without
+// reading it back, how many voxels they occupy: that count lives in the cell
+// tables on the device.  The launches of a step depend only on which
+// simulations hold cells and on this bound of the occupied voxels (the
+// sources kernels' grid; they stop at the true count, read on the device),
+// so a step graph stays valid across uploads that keep both.
+int occ_bound(const vl_ctx *ctx)
+{
+    long long b = 0;
+    for (const SimHost &s : ctx->sims) b += s.n_cells;
+    return (int)std::min<long long>(b, INT_MAX);
+}
+
+std::vector<int> cells_plan(const vl_ctx *ctx)
+{
+    std::vector<int> p{occ_bound(ctx)};
+    for (const SimHost &s : ctx->sims) p.push_back(s.n_cells > 0);
+    return p;
 }
 
 // phase: kStepWhole a complete step; with carried sources kStepCarryFirst
@@ -301,8 +324,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
     hipStream_t st = ctx->stream;
     const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
     const int nsubs = (int)ctx->subs.size();
-    int total_occ = 0;
-    for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+    const int total_occ = occ_bound(ctx);
     int rc;
     if (ctx->precision == VL_F32) {
         float *field = (float *)ctx->field;
@@ -353,7 +375,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
             bool nt = L.axis == 2 && vl::kCaps[L.cap_idx] >= 160;
             for (int i = 0; nt && src.enabled && i < L.count; ++i) {
                 const SimHost &sh = ctx->sims[ctx->subs[ctx->itable[L.ids_off + i]].sim];
-                if (sh.n_occ > 0 && !(phase != kStepWhole && sh.xs_base >= 0)) nt = false;
+                if (sh.n_cells > 0 && !(phase != kStepWhole && sh.xs_base >= 0)) nt = false;
             }
             return timed(ctx, VL_K_SWEEP_X + L.axis, [&] {
                 return vl::launch_sweep_f32(L.axis, L.cap_idx, d, subs, coef, field, nullptr, src, carry, nt, st);
@@ -390,7 +412,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
         // solve applies them
         bool thin = false;
         for (const SimHost &s : ctx->sims)
-            thin = thin || (s.n_occ > 0 && z_skipped(ctx, s.sub0, 2) && (phase == kStepWhole || s.xs_base < 0));
+            thin = thin || (s.n_cells > 0 && z_skipped(ctx, s.sub0, 2) && (phase == kStepWhole || s.xs_base < 0));
         if (fused && thin) {
             rc = timed(ctx, VL_K_SOURCES, [&] {
                 return vl::launch_sources_thin_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
@@ -458,8 +480,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
 // standalone kernel over the simulations whose sources were carried.
 int enqueue_carried_sources(vl_ctx *ctx)
 {
-    int total_occ = 0;
-    for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+    const int total_occ = occ_bound(ctx);
     return timed(ctx, VL_K_SOURCES, [&] {
         return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
                                       ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
@@ -1215,17 +1236,23 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
         }
     }
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    drop_graph(ctx);
+    // The step graphs read the cell tables from the workspace; they are
+    // captured again only when the launches they hold change.
+    const std::vector<int> plan0 = cells_plan(ctx);
     hipStream_t st = ctx->stream;
     s.n_cells = n;
     s.n_occ = 0;
     s.n_out = 0;
+    if (cells_plan(ctx) != plan0) drop_graph(ctx);
+    vl::SimCells *cells_dev = ctx->at<vl::SimCells>(ctx->o_cells);
     if (s.zl_base >= 0)
         VL_HIP(hipMemsetAsync(ctx->at<int>(ctx->o_line_start) + s.zl_base, 0,
                               sizeof(int) * ((size_t)s.n[0] * s.n[1] + 1), st));
     if (n == 0) {
         if (n_out_of_domain) *n_out_of_domain = 0;
-        return upload_cell_tables(ctx);
+        VL_HIP(vl::launch_finish_upload(nullptr, cells_dev, sim, ctx->n_sims, s.xs_base,
+                                        ctx->at<int>(ctx->o_occ_prefix), st));
+        return VL_OK;
     }
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_pos, pos, sizeof(double) * 3 * n, kind, st));
     VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_V, V, sizeof(double) * n, kind, st));
@@ -1275,15 +1302,21 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
                                  zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
                                  zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
                                  zorder ? ctx->at<int>(ctx->o_cell_of) + s.occ_base : nullptr, st));
-    int host_counters[2] = {0, 0};
-    VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-    VL_HIP(hipStreamSynchronize(st));
-    const int n_out = host_counters[0];
-    const int n_occ = host_counters[1];
-    s.n_occ = n_occ;
-    s.n_out = n_out;
-    if (n_out_of_domain) *n_out_of_domain = n_out;
-    return upload_cell_tables(ctx);
+    VL_HIP(vl::launch_finish_upload(counters, cells_dev, sim, ctx->n_sims, s.xs_base,
+                                    ctx->at<int>(ctx->o_occ_prefix), st));
+    // From device arrays with no count asked for, nothing waits: the upload
+    // runs on the stream ahead of the next steps.  Otherwise the counts are
+    // read back (from host arrays this also ends the host copies before the
+    // caller may change its arrays).
+    if (n_out_of_domain || !on_device) {
+        int host_counters[2] = {0, 0};
+        VL_HIP(hipMemcpyAsync(host_counters, counters, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+        VL_HIP(hipStreamSynchronize(st));
+        s.n_out = host_counters[0];
+        s.n_occ = host_counters[1];
+        if (n_out_of_domain) *n_out_of_domain = s.n_out;
+    }
+    return VL_OK;
 }
 
 int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
@@ -1825,8 +1858,7 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
         VL_HIP(hipMemsetAsync(dS_dev, 0, sizeof(double) * n_cells_sub, st));
         VL_HIP(hipMemsetAsync(dU_dev, 0, sizeof(double) * n_cells_sub, st));
     }
-    int total_occ = 0;
-    for (const SimHost &s : ctx->sims) total_occ += s.n_occ;
+    const int total_occ = occ_bound(ctx);
     const SubDev *subs = ctx->at<SubDev>(ctx->o_subs);
     const float2 *coef = ctx->at<float2>(ctx->o_coef32);
     float *w = (float *)(aws + A.w);

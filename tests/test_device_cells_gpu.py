@@ -43,10 +43,12 @@ def _device(ctx, a):
     return ctx.torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(ctx.device)
 
 
-def _run(specs, moves, every, n_steps, from_device, x_lanes):
+def _run(specs, moves, every, n_steps, from_device, x_lanes, count=True, sources=None):
     ctx = vb.Context(specs, device="cuda:0")
     try:
         ctx.set_option(vb.VL_OPT_X_LANES, x_lanes)
+        if sources is not None:
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, sources)
         for k, s in enumerate(specs):
             ctx.set_field(k, s.rho0)
         outs = []
@@ -58,7 +60,7 @@ def _run(specs, moves, every, n_steps, from_device, x_lanes):
                     if from_device:
                         n_out = ctx.upload_cells_device(k, _device(ctx, moves[k][m - 1]), _device(ctx, c.V),
                                                         _device(ctx, c.S), _device(ctx, c.U),
-                                                        _device(ctx, c.rho_star))
+                                                        _device(ctx, c.rho_star), count_out=count)
                     else:
                         n_out = ctx.upload_cells(k, W.Cells(pos=moves[k][m - 1], V=c.V, S=c.S, U=c.U,
                                                             rho_star=c.rho_star))
@@ -98,6 +100,25 @@ def test_moving_cells_uploaded_from_device(x_lanes):
     for k, spec in enumerate(specs):
         assert np.array_equal(fd[k], fh[k]), f"sim {k}: device and host uploads differ"
         assert_close(fd[k], _oracle(spec, moves[k], every, n_steps), 1e-5, f"moving cells sim {k}")
+
+
+@pytest.mark.parametrize("sources", [0, 1, 2])
+def test_moving_cells_without_reading_counts_back(sources):
+    """Uploads that ask for no count of cells off the grid wait for nothing
+    after the check of the arrays, and keep the step graphs (the cell counts
+    stay the same from move to move): the fields equal those of uploads that
+    read the counts back (and rebuild nothing), bitwise, in every source
+    placement, and the oracle's."""
+    specs = [_spec((150, 12, 9), 2, "mixed", 300, 5), _spec((33, 20, 17), 1, "neumann", 150, 6)]
+    every, n_moves = 2, 4
+    moves = [_moves(s, n_moves, 91 + k) for k, s in enumerate(specs)]
+    n_steps = every * (n_moves + 1)
+    fa, out_a = _run(specs, moves, every, n_steps, True, 1, count=False, sources=sources)
+    fb, out_b = _run(specs, moves, every, n_steps, True, 1, count=True, sources=sources)
+    assert all(o is None for o in out_a) and any(o > 0 for o in out_b)
+    for k, spec in enumerate(specs):
+        assert np.array_equal(fa[k], fb[k]), f"sim {k}: uploads with and without counts differ"
+        assert_close(fa[k], _oracle(spec, moves[k], every, n_steps), 1e-5, f"moving cells sim {k}, mode {sources}")
 
 
 def test_device_upload_rejects_bad_cells_and_keeps_the_old_ones():
