@@ -286,30 +286,65 @@ rs_hist_kernel(const unsigned long long *__restrict__ keys, const int *__restric
     if (threadIdx.x < kRsRadix) hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// In-place exclusive scan of a[0..m) by one workgroup; *total (if given)
-// receives the sum.
-__global__ void __launch_bounds__(1024) scan_small_kernel(unsigned *__restrict__ a, int m, int *total)
+// In-place exclusive scan of a[0..m) by one workgroup of 1024 threads, in
+// rounds of kScanChunk entries: each round is read into LDS with coalesced
+// loads, thread t scans its eight consecutive entries, the thread sums are
+// scanned within each wave by shuffles and across the 16 waves through LDS,
+// and the round goes back with coalesced stores, offset by the earlier
+// rounds' sum.  *total (if given) receives the sum of all entries.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+__global__ void __launch_bounds__(kScanThreads) scan_small_kernel(unsigned *__restrict__ a, int m, int *total)
 {
-    __shared__ unsigned part[1024];
-    const int per = (m + 1023) / 1024;
-    const int b = min(m, (int)threadIdx.x * per), e = min(m, b + per);
-    unsigned sum = 0;
-    for (int i = b; i < e; ++i) sum += a[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __shared__ unsigned buf[kScanChunk];
+    __shared__ unsigned wsum[kScanThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    unsigned carry = 0;  // sum of the earlier rounds
+    for (int c0 = 0; c0 < m; c0 += kScanChunk) {
+        const int len = min(kScanChunk, m - c0);
+        for (int i = t; i < len; i += kScanThreads) buf[i] = a[c0 + i];
         __syncthreads();
-        part[threadIdx.x] += v;
+        unsigned v[kScanPer];
+        unsigned sum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = kScanPer * t + j;
+            v[j] = i < len ? buf[i] : 0u;
+            sum += v[j];
+        }
+        unsigned x = sum;  // inclusive scan of the thread sums within the wave
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const unsigned y = __shfl_up(x, off, kWave);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) wsum[w] = x;
         __syncthreads();
+        if (t < kWave) {  // inclusive scan of the wave sums
+            unsigned q = t < kScanThreads / kWave ? wsum[t] : 0u;
+#pragma unroll
+            for (int off = 1; off < kScanThreads / kWave; off <<= 1) {
+                const unsigned y = __shfl_up(q, off, kWave);
+                if (t >= off) q += y;
+            }
+            if (t < kScanThreads / kWave) wsum[t] = q;
+        }
+        __syncthreads();
+        unsigned run = carry + (w ? wsum[w - 1] : 0u) + (x - sum);
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = kScanPer * t + j;
+            if (i < len) buf[i] = run;
+            run += v[j];
+        }
+        carry += wsum[kScanThreads / kWave - 1];
+        __syncthreads();
+        for (int i = t; i < len; i += kScanThreads) a[c0 + i] = buf[i];
+        __syncthreads();  // buf and wsum are refilled by the next round
     }
-    unsigned run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int i = b; i < e; ++i) {
-        const unsigned h = a[i];
-        a[i] = run;
-        run += h;
-    }
-    if (total && threadIdx.x == 1023) *total = (int)part[1023];
+    if (total && t == 0) *total = (int)carry;
 }
 
 // c[d][t]: thread t's count of digit d on entry, its exclusive prefix over the
@@ -379,8 +414,7 @@ hipError_t launch_radix_sort(unsigned long long *keys, unsigned long long *alt, 
                              int bits, unsigned *hist, hipStream_t st)
 {
     if (n_cap <= 0 || bits <= 0) return hipSuccess;
-    int passes = (bits + 3) / 4;
-    passes += passes & 1;  // an even number of passes leaves the result in keys
+    const int passes = (bits + 3) / 4;
     if (lo_bit < 0 || lo_bit + 4 * passes > 64) return hipErrorInvalidValue;
     const int nb = (n_cap + kRsTile - 1) / kRsTile;
     unsigned long long *src = keys, *dst = alt;
@@ -393,7 +427,12 @@ hipError_t launch_radix_sort(unsigned long long *keys, unsigned long long *alt, 
         src = dst;
         dst = tmp;
     }
-    return hipGetLastError();
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    // after an odd number of passes the sorted keys are in alt (the first
+    // *n_dev of them matter; n_cap bounds them)
+    if (passes & 1) return hipMemcpyAsync(keys, alt, sizeof(unsigned long long) * (size_t)n_cap,
+                                          hipMemcpyDeviceToDevice, st);
+    return hipSuccess;
 }
 
 // Occupied voxels of the sorted keys (the first n_in, counts[2], are inside

@@ -1254,11 +1254,21 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
                                         ctx->at<int>(ctx->o_occ_prefix), st));
         return VL_OK;
     }
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_pos, pos, sizeof(double) * 3 * n, kind, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_V, V, sizeof(double) * n, kind, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_S, S, sizeof(double) * n * ns, kind, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_U, U, sizeof(double) * n * ns, kind, st));
-    VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_RS, rho_star, sizeof(double) * n * ns, kind, st));
+    // Host arrays are staged in the workspace; device arrays are read where
+    // they are (only the binning kernels below read them).
+    const double *pos_d = pos, *V_d = V, *S_d = S, *U_d = U, *RS_d = rho_star;
+    if (!on_device) {
+        VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_pos, pos, sizeof(double) * 3 * n, kind, st));
+        VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_V, V, sizeof(double) * n, kind, st));
+        VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_S, S, sizeof(double) * n * ns, kind, st));
+        VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_U, U, sizeof(double) * n * ns, kind, st));
+        VL_HIP(hipMemcpyAsync(ctx->ws + ctx->o_RS, rho_star, sizeof(double) * n * ns, kind, st));
+        pos_d = ctx->at<double>(ctx->o_pos);
+        V_d = ctx->at<double>(ctx->o_V);
+        S_d = ctx->at<double>(ctx->o_S);
+        U_d = ctx->at<double>(ctx->o_U);
+        RS_d = ctx->at<double>(ctx->o_RS);
+    }
     // Binning on the device, its counts kept there (no host round trip
     // between the kernels): keys, stable radix sort by voxel, occupied-voxel
     // segments, the z-line order (FP32) and x-line starts, composites.  One
@@ -1267,7 +1277,7 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
     unsigned *hist = ctx->at<unsigned>(ctx->o_rs_hist);
     VL_HIP(vl::launch_upload_counts(counters, n, st));
     unsigned long long *keys = ctx->at<unsigned long long>(ctx->o_keys);
-    VL_HIP(vl::launch_cell_keys(ctx->at<double>(ctx->o_pos), n, s.n[0], s.n[1], s.n[2], s.lo[0], s.lo[1],
+    VL_HIP(vl::launch_cell_keys(pos_d, n, s.n[0], s.n[1], s.n[2], s.lo[0], s.lo[1],
                                 s.lo[2], s.h[0], s.h[1], s.h[2], keys, counters, st));
     // voxel indices lie below n_vox, and the out-of-domain key (all ones) above
     int vbits = 0;
@@ -1294,8 +1304,7 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
     }
     const double vvox = s.h[0] * s.h[1] * s.h[2];
     VL_HIP(vl::launch_composites(keys, ctx->at<int>(ctx->o_seg_start) + s.occ_base, counters, n, s.ns,
-                                 ctx->at<double>(ctx->o_V), ctx->at<double>(ctx->o_S), ctx->at<double>(ctx->o_U),
-                                 ctx->at<double>(ctx->o_RS), ctx->dt, vvox, pos_idx,
+                                 V_d, S_d, U_d, RS_d, ctx->dt, vvox, pos_idx,
                                  zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
                                  zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr, s.max_cells,
                                  ctx->at<double2>(ctx->o_ab) + s.ab_base,

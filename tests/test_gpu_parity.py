@@ -224,6 +224,18 @@ def test_fp32_many_cells_in_one_voxel():
     assert_close(got, run_oracle(spec, 5), 1e-5, "300 cells in one voxel")
 
 
+@pytest.mark.parametrize("sources_mode", [1, 2])
+def test_fp32_over_a_million_cells(sources_mode):
+    """1.2e6 cells, about 50 per voxel of a 40 x 30 x 20 grid: the binning's
+    radix-sort histograms (16 digits per block of 2048 keys) pass the 8192
+    entries that the scan takes per round, so the scan runs more than one
+    round; sources in the z sweep and carried into the x solve."""
+    spec = _spec((40, 30, 20), 2, "mixed", 1_200_000, "f32", 41)
+    (got,), n_out = run_gpu([spec], 3, x_lanes=1, sources_mode=sources_mode)
+    assert n_out == [1]  # the one cell placed outside the grid
+    assert_close(got, run_oracle(spec, 3), 1e-5, f"1.2e6 cells, sources mode {sources_mode}")
+
+
 def test_all_cells_outside():
     spec = _spec((8, 8, 8), 1, "mixed", 5, "f32", 6)
     spec.cells.pos[:] = np.array(spec.lo) - 10.0
