@@ -144,10 +144,12 @@ def time_moving_cells(ctx, wl, steps: int, every: int):
     arrays every `every` steps (vl_upload_cells_dev: voxel index, sort,
     composites; the positions are prepared on the device beforehand, a small
     random walk per move; no count of cells off the grid is asked for, so an
-    upload waits for the stream only to check the arrays).  Returns (seconds,
-    uploads, host seconds in the upload calls, which include waiting for the
-    steps queued before them)."""
+    upload waits for the stream only to check the arrays; a forward run, so
+    the uploads skip the per-cell tables only the adjoint reads).  Returns
+    (seconds, uploads, host seconds in the upload calls, which include waiting
+    for the steps queued before them)."""
     import torch
+    from paper_2110_13368_amd import binding as vb
     n_moves = max(steps // every, 1)
     g = torch.Generator(device=ctx.device).manual_seed(211013368 + 50)
     dev = []
@@ -158,6 +160,7 @@ def time_moving_cells(ctx, wl, steps: int, every: int):
         walk = torch.randn((n_moves,) + tuple(pos0.shape), generator=g, device=ctx.device,
                            dtype=torch.float64) * (0.5 * s.h[0])
         dev.append((pos0 + torch.cumsum(walk, 0), t(c.V), t(c.S), t(c.U), t(c.rho_star)))
+    ctx.set_option(vb.VL_OPT_ADJOINT_TABLES, 0)
     torch.cuda.synchronize()
     t_up = 0.0
     t0 = time.perf_counter()
@@ -172,7 +175,9 @@ def time_moving_cells(ctx, wl, steps: int, every: int):
         done += take
     ctx.sync()
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, n_moves, t_up
+    elapsed = time.perf_counter() - t0
+    ctx.set_option(vb.VL_OPT_ADJOINT_TABLES, 1)
+    return elapsed, n_moves, t_up
 
 
 def kernel_profile(ctx, steps: int):
@@ -496,6 +501,7 @@ def run_workload(args, config: str, cpu: bool, copy_ref: bool, fp64: bool = True
         moving = {"every_steps": args.move_cells_every, "steps": args.steps, "uploads": n_up,
                   "value": E * args.steps / t_mv, "unit": "voxel-substrate updates/s",
                   "ms_per_rebinning": round(1e3 * (t_mv - elapsed) / n_up, 3),
+                  "adjoint_tables": False,
                   "note": "cells moved on the device and re-binned (vl_upload_cells_dev) every every_steps steps, "
                           "inside the timed loop; value counts the diffusion updates only; ms_per_rebinning is the "
                           "loop's time beyond the same steps with fixed cells, per upload"}

@@ -342,6 +342,13 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * the device), large ones keep more loads in flight per wave.  Fields do not
  * depend on it; vl_tune times the candidates. */
 #define VL_OPT_X_LANE_LINES 8
+/* VL_OPT_ADJOINT_TABLES (FP32 path, default 1): a cell upload also writes the
+ * per-cell tables that only vl_adjoint reads (each cell's a_i, b_i, k_i
+ * rho*_i and k_i, in voxel order; about 24 bytes per cell and substrate).
+ * 0 skips them, for callers that only step forward: the fields do not
+ * change, and vl_adjoint returns VL_E_STATE while any simulation holds cells
+ * uploaded without them.  It applies to the uploads that follow. */
+#define VL_OPT_ADJOINT_TABLES 9
 /* Launch-shape options (no passage of the paper defines them; fields do not
  * depend on them beyond rounding, and the placements of the sources and the
  * x+y-per-plane option give bitwise equal fields).  Unknown options and

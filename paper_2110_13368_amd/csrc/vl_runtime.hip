@@ -71,6 +71,7 @@ struct SimHost {
     int occ_base = 0, comp_base = 0, ab_base = 0, zl_base = -1;
     int xs_base = -1;  // x-line starts of the carried sources, -1 when not eligible
     int n_cells = 0;        // cells of the last upload
+    bool adj_ok = true;     // its per-cell tables of the adjoint were written
     int n_occ = 0, n_out = 0;  // its occupied voxels and cells off the grid, as last read back (the
                                // device's cell tables hold the occupied count of every upload)
     long long nvox() const { return (long long)n[0] * n[1] * n[2]; }
@@ -136,6 +137,7 @@ struct vl_ctx {
     size_t n_xl32 = 0;
     size_t xy_lds_max = 0;
     bool xcd_order = true;
+    bool adj_tables = true;  // uploads write the per-cell tables of the adjoint
 
     // one-launch step (FP32): queue over all tiles of the three sweeps
     int step_mode = VL_MODE_LAUNCHES;
@@ -1243,6 +1245,10 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
     s.n_cells = n;
     s.n_occ = 0;
     s.n_out = 0;
+    // FP32: the per-cell tables only the adjoint reads (the FP64 path steps
+    // with the per-cell (a, b) and always writes them)
+    const bool adj = ctx->precision == VL_F64 || ctx->adj_tables;
+    s.adj_ok = adj || n == 0;
     if (cells_plan(ctx) != plan0) drop_graph(ctx);
     vl::SimCells *cells_dev = ctx->at<vl::SimCells>(ctx->o_cells);
     if (s.zl_base >= 0)
@@ -1307,10 +1313,10 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
                                  V_d, S_d, U_d, RS_d, ctx->dt, vvox, pos_idx,
                                  zorder ? ctx->at<float2>(ctx->o_comp) + s.comp_base : nullptr,
                                  zorder ? ctx->at<float2>(ctx->o_comp_v) + s.comp_base : nullptr, s.max_cells,
-                                 ctx->at<double2>(ctx->o_ab) + s.ab_base,
-                                 zorder ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
-                                 zorder ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
-                                 zorder ? ctx->at<int>(ctx->o_cell_of) + s.occ_base : nullptr, st));
+                                 adj ? ctx->at<double2>(ctx->o_ab) + s.ab_base : nullptr,
+                                 zorder && adj ? ctx->at<double>(ctx->o_krs) + s.ab_base : nullptr,
+                                 zorder && adj ? ctx->at<double>(ctx->o_kcell) + s.occ_base : nullptr,
+                                 zorder && adj ? ctx->at<int>(ctx->o_cell_of) + s.occ_base : nullptr, st));
     VL_HIP(vl::launch_finish_upload(counters, cells_dev, sim, ctx->n_sims, s.xs_base,
                                     ctx->at<int>(ctx->o_occ_prefix), st));
     // From device arrays with no count asked for, nothing waits: the upload
@@ -1493,6 +1499,11 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         ctx->xcd_order = value == 1;
         return VL_OK;
     }
+    if (option == VL_OPT_ADJOINT_TABLES) {
+        if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_ADJOINT_TABLES takes 0 or 1");
+        ctx->adj_tables = value == 1;
+        return VL_OK;
+    }
     if (option == VL_OPT_WAIT_LIMIT_US) {
         if (value < 0) return fail(VL_E_ARG, "VL_OPT_WAIT_LIMIT_US must be >= 0");
         if (ctx->wait_limit_us != value) drop_graph(ctx);
@@ -1515,6 +1526,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     case VL_OPT_FUSE_XY: *value = ctx->fuse_xy ? 1 : 0; return VL_OK;
     case VL_OPT_X_LANES: *value = ctx->x_lanes; return VL_OK;
     case VL_OPT_X_LANE_LINES: *value = ctx->xl_lpw; return VL_OK;
+    case VL_OPT_ADJOINT_TABLES: *value = ctx->adj_tables ? 1 : 0; return VL_OK;
     default: return fail(VL_E_ARG, "unknown option");
     }
 }
@@ -1836,6 +1848,9 @@ int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, co
     long long n_cells_sub = 0;
     for (const SimHost &s : ctx->sims) n_cells_sub += (long long)s.n_cells * s.ns;
     if (n_cells_sub > 0 && (!dS_dev || !dU_dev)) return fail(VL_E_ARG, "dS and dU are required when cells exist");
+    for (const SimHost &s : ctx->sims)
+        if (s.n_cells > 0 && !s.adj_ok)
+            return fail(VL_E_STATE, "cells were uploaded with VL_OPT_ADJOINT_TABLES 0: upload them again with 1");
     const int K = std::min(ckpt_every, std::max(n_steps, 1));
     const AdjLayout A = adj_layout(ctx, n_steps, K);
     char *aws = (char *)adj_workspace;

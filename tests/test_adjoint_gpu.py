@@ -452,3 +452,35 @@ def test_autograd_keeps_cells_moved_on_the_device():
         _close(U2.grad.cpu().numpy().reshape(-1, spec.n_sub), o["U"], "dU with moved cells")
     finally:
         ctx.close()
+
+
+def test_uploads_without_adjoint_tables():
+    """VL_OPT_ADJOINT_TABLES 0: uploads skip the per-cell tables only the
+    adjoint reads.  The forward fields are bitwise those of uploads that write
+    them; vl_adjoint refuses (VL_E_STATE) until the cells are uploaded again
+    with the tables, and then matches the oracle's adjoint."""
+    spec, target = _case(1301, (17, 13, 10), n_cells=40)
+    n_steps = 4
+    fields = []
+    for tables in (1, 0):
+        ctx = vb.Context([spec], device="cuda:0")
+        try:
+            ctx.set_option(vb.VL_OPT_ADJOINT_TABLES, tables)
+            ctx.upload_cells(0, spec.cells)
+            ctx.step(n_steps)
+            ctx.sync()
+            fields.append(ctx.get_field(0).copy())
+            if tables == 0:
+                ctx.set_field(0, spec.rho0)
+                with pytest.raises(vb.VoxlodError) as e:
+                    ctx.adjoint(n_steps, 2, [np.zeros(spec.field_shape, np.float32)])
+                assert e.value.code == vb.VL_E_STATE
+                ctx.set_option(vb.VL_OPT_ADJOINT_TABLES, 1)
+                ctx.upload_cells(0, spec.cells)
+                o, r = _oracle_grads(spec, target, O.DECAY_ONCE, n_steps)
+                g = ctx.adjoint(n_steps, 2, [r.astype(np.float32)])
+                g = {k: (v.double().cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)) for k, v in g[0].items()}
+                _compare(g, o, "after re-upload with the tables")
+        finally:
+            ctx.close()
+    assert np.array_equal(fields[0], fields[1])
