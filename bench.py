@@ -53,7 +53,8 @@ def source_digest(files) -> str:
 
 
 def measured_traffic(workload: str, kernel: str, launch: dict | None = None):
-    """HBM bytes per launch of a kernel from the committed FETCH_SIZE /
+    """HBM bytes of a sweep kind per step (its launches in one step, the basis
+    of the roofline's achieved rate) from the committed FETCH_SIZE /
     WRITE_SIZE measurements (scaled by the copy-kernel calibration), or None
     when there is none for this workload and launch configuration, or the
     kernel's sources changed since the counters were taken."""
@@ -194,7 +195,7 @@ def copy_reference(nbytes: int, reps: int = 20):
     """Device-to-device copies of nbytes: torch's elementwise copy and the
     library's copy probe (vl_copy_probe) with 4- and 16-byte accesses per
     lane, ordinary or non-temporal loads and stores, between two buffers and
-    in place.  The fastest is the
+    in place, and in 64 KiB tiles loaded whole before they are stored.  The fastest is the
     practical bandwidth ceiling for a sweep (which reads and writes every
     element once); each is a kernel of known traffic (nbytes read, nbytes
     written per launch) that scales the FETCH_SIZE / WRITE_SIZE counters."""
@@ -224,6 +225,9 @@ def copy_reference(nbytes: int, reps: int = 20):
         for nt in (0, 3):
             probe[f"in_place_width{width}_nt{nt}"] = rate(
                 lambda: vb.vl_copy_probe(dst.data_ptr(), dst.data_ptr(), nbytes, width, nt, stream))
+    # 64 KiB tiles, each loaded whole before it is stored (a sweep tile's shape)
+    probe["tile64k"] = rate(lambda: vb.vl_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, 16, 4, stream))
+    probe["tile64k_in_place"] = rate(lambda: vb.vl_copy_probe(dst.data_ptr(), dst.data_ptr(), nbytes, 16, 4, stream))
     if not torch.equal(dst, src):
         raise RuntimeError("vl_copy_probe: destination differs from source")
     out["vl_copy_probe_GBps"] = probe

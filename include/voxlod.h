@@ -408,10 +408,12 @@ int vl_kernel_stats(vl_ctx *ctx, int kind, long long *launches, double *total_ms
  * copies bytes from src to dst, both device memory, 16-byte aligned, either
  * the same buffer (dst == src: every element read and written back in place,
  * the way a sweep updates its field) or not overlapping at all, bytes a
- * multiple of 16, with width-byte accesses per lane (4,
- * 8 or 16) and, per bit of nontemporal, non-temporal loads (bit 0) and
- * stores (bit 1), asynchronously on stream (hipStream_t as void*, NULL = the
- * null stream).  Each sweep of vl_step reads and writes every element once,
+ * multiple of 16, with width-byte accesses per lane (4, 8 or 16) and, per
+ * bit of nontemporal (0 to 3), non-temporal loads (bit 0) and stores (bit 1);
+ * nontemporal 4 (width 16) copies in 64 KiB tiles instead, each workgroup
+ * loading its whole tile before storing it, the access shape of a sweep
+ * tile.  Asynchronous on stream (hipStream_t as void*, NULL = the null
+ * stream).  Each sweep of vl_step reads and writes every element once,
  * so a copy of the field's bytes is the practical ceiling a sweep is measured
  * against; it is also the kernel of known traffic that scales the HBM byte
  * counters.  The caller owns both buffers.  VL_E_ARG for a bad argument

@@ -66,6 +66,30 @@ __global__ void __launch_bounds__(kCopyThreads) rewrite_probe_kernel(T *buf, siz
     }
 }
 
+// Tiles of kTileThreads x kTileItems 16-byte values (64 KiB) per workgroup,
+// each read whole into registers before any of it is written: the access
+// shape of a sweep tile, which loads its lines, solves, then stores them.
+// Source and destination may be the same buffer (each thread writes back
+// only what it read).
+constexpr int kTileThreads = 256;
+constexpr int kTileItems = 16;
+
+__global__ void __launch_bounds__(kTileThreads) tile_probe_kernel(const cp_u32x4 *src, cp_u32x4 *dst, size_t n)
+{
+    const size_t base = (size_t)blockIdx.x * (kTileThreads * kTileItems) + threadIdx.x;
+    cp_u32x4 r[kTileItems];
+#pragma unroll
+    for (int u = 0; u < kTileItems; ++u) {
+        const size_t i = base + (size_t)u * kTileThreads;
+        if (i < n) r[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kTileItems; ++u) {
+        const size_t i = base + (size_t)u * kTileThreads;
+        if (i < n) dst[i] = r[u];
+    }
+}
+
 template <typename T>
 hipError_t launch_typed(const void *src, void *dst, size_t bytes, int nt, hipStream_t st)
 {
@@ -95,11 +119,19 @@ hipError_t launch_typed(const void *src, void *dst, size_t bytes, int nt, hipStr
 }  // namespace
 
 // width: bytes per lane access (4, 8 or 16); nt: bit 0 non-temporal loads,
-// bit 1 non-temporal stores; src == dst rewrites the buffer in place.  bytes is a multiple of 16 and below 2^32 *
+// bit 1 non-temporal stores, or 4 for 64 KiB tiles loaded whole before they
+// are stored (width 16); src == dst rewrites the buffer in place.  bytes is a multiple of 16 and below 2^32 *
 // (kCopyThreads * kCopyUnroll) * width (checked by the caller).
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, int width, int nt, hipStream_t st)
 {
     if (bytes == 0) return hipSuccess;
+    if (nt == 4) {
+        const size_t n = bytes / 16;
+        const size_t per = (size_t)kTileThreads * kTileItems;
+        hipLaunchKernelGGL(tile_probe_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(kTileThreads), 0, st,
+                           (const cp_u32x4 *)src, (cp_u32x4 *)dst, n);
+        return hipGetLastError();
+    }
     if (width == 4) return launch_typed<unsigned>(src, dst, bytes, nt, st);
     if (width == 8) return launch_typed<cp_u32x2>(src, dst, bytes, nt, st);
     return launch_typed<cp_u32x4>(src, dst, bytes, nt, st);

@@ -1962,7 +1962,8 @@ int vl_copy_probe(void *dst, const void *src, size_t bytes, int width, int nonte
 {
     if (!dst || !src) return fail(VL_E_ARG, "vl_copy_probe: null buffer");
     if (width != 4 && width != 8 && width != 16) return fail(VL_E_ARG, "vl_copy_probe: width must be 4, 8 or 16");
-    if (nontemporal < 0 || nontemporal > 3) return fail(VL_E_ARG, "vl_copy_probe: nontemporal must be in [0, 3]");
+    if (nontemporal < 0 || nontemporal > 4) return fail(VL_E_ARG, "vl_copy_probe: nontemporal must be in [0, 4]");
+    if (nontemporal == 4 && width != 16) return fail(VL_E_ARG, "vl_copy_probe: tiles (4) take width 16");
     if (bytes % 16 != 0) return fail(VL_E_ARG, "vl_copy_probe: bytes must be a multiple of 16");
     if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return fail(VL_E_ARG, "vl_copy_probe: buffers must be 16-byte aligned");
     if (bytes / (size_t)width / 1024u >= (1ull << 31)) return fail(VL_E_ARG, "vl_copy_probe: bytes too large");

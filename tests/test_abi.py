@@ -160,7 +160,8 @@ def test_copy_probe_rejects_bad_arguments_on_the_host():
     assert _code(vb.vl_copy_probe, 0, 256, 1024) == vb.VL_E_ARG  # null destination
     assert _code(vb.vl_copy_probe, 4096, 0, 1024) == vb.VL_E_ARG  # null source
     assert _code(vb.vl_copy_probe, 4096, 8192, 1024, 2) == vb.VL_E_ARG  # width
-    assert _code(vb.vl_copy_probe, 4096, 8192, 1024, 16, 4) == vb.VL_E_ARG  # non-temporal bits
+    assert _code(vb.vl_copy_probe, 4096, 8192, 1024, 16, 5) == vb.VL_E_ARG  # non-temporal bits
+    assert _code(vb.vl_copy_probe, 4096, 8192, 1024, 4, 4) == vb.VL_E_ARG  # tiles take width 16
     assert _code(vb.vl_copy_probe, 4096, 8192, 1000) == vb.VL_E_ARG  # not a multiple of 16
     assert _code(vb.vl_copy_probe, 4100, 8192, 1024) == vb.VL_E_ARG  # misaligned
     assert _code(vb.vl_copy_probe, 4096, 4608, 1024) == vb.VL_E_ARG  # overlapping

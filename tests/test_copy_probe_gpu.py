@@ -35,3 +35,20 @@ def test_copy_probe_in_place_leaves_the_buffer_unchanged(width, nt):
     vb.vl_copy_probe(buf.data_ptr(), buf.data_ptr(), nbytes, width, nt, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert torch.equal(buf, ref)
+
+
+@pytest.mark.parametrize("nbytes", [16, (64 << 10) - 16, (1 << 20) + 16 * 37])
+def test_copy_probe_tiles_copy_exactly_and_in_place(nbytes):
+    import torch
+    n = nbytes // 4
+    src = torch.randint(-2 ** 31, 2 ** 31 - 1, (n + 64,), dtype=torch.int32, device="cuda")
+    dst = torch.full((n + 64,), 7, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    print(f"copy probe tiles: {nbytes} bytes", flush=True)
+    vb.vl_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, 16, 4, st)
+    ref = src.clone()
+    vb.vl_copy_probe(src.data_ptr(), src.data_ptr(), nbytes, 16, 4, st)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n], src[:n])
+    assert bool((dst[n:] == 7).all())
+    assert torch.equal(src, ref)
