@@ -154,6 +154,19 @@ int vl_set_substrates(vl_ctx *ctx, int sim, int n_sub, const double *D,
 int vl_set_boundary(vl_ctx *ctx, int sim, int sub, int face, int kind, double value);
 int vl_reserve_cells(vl_ctx *ctx, int sim, int max_cells);
 
+/* Change one simulation's cell capacity after vl_finalize (the cells i of
+ * Eq. (1)'s source sum, for agent populations that grow past the capacity
+ * reserved at set-up; the paper's hybrid model adds and removes cells as it
+ * runs).  Waits for the bound stream, lays the workspace out again for the
+ * new capacities and reports its size in *workspace_bytes (may be NULL); the
+ * field layout does not change.  The context is then unbound: call vl_bind
+ * again, with the same field (its values are kept) and a workspace of that
+ * size, and upload every simulation's cells again (vl_bind clears them).
+ * The old workspace is the caller's to free once vl_bind returns.
+ * VL_E_STATE before vl_finalize or while a snapshot is in flight; VL_E_ARG
+ * for max_cells outside [0, 2^24]. */
+int vl_resize_cells(vl_ctx *ctx, int sim, int max_cells, size_t *workspace_bytes);
+
 /* Fix the layout for time step dt > 0 and report the sizes the caller must
  * allocate: *field_elems elements of the context's precision and
  * *workspace_bytes bytes (256-byte aligned device memory).  Section

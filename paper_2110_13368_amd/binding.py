@@ -49,6 +49,7 @@ SIGNATURES = {
     "vl_set_substrates": (_i, [_vp, _i, _i, _dp, _dp]),
     "vl_set_boundary": (_i, [_vp, _i, _i, _i, _i, _d]),
     "vl_reserve_cells": (_i, [_vp, _i, _i]),
+    "vl_resize_cells": (_i, [_vp, _i, _i, C.POINTER(C.c_size_t)]),
     "vl_finalize": (_i, [_vp, _d, C.POINTER(_sz), C.POINTER(_sz)]),
     "vl_bind": (_i, [_vp, _vp, _vp, _vp]),
     "vl_field_offset": (_i, [_vp, _i, C.POINTER(_sz)]),
@@ -156,6 +157,14 @@ def vl_set_boundary(ctx, sim, sub, face, kind, value) -> None:
 
 def vl_reserve_cells(ctx, sim, max_cells) -> None:
     _check(lib().vl_reserve_cells(ctx, int(sim), int(max_cells)), "vl_reserve_cells")
+
+
+def vl_resize_cells(ctx, sim, max_cells) -> int:
+    """New cell capacity after vl_finalize; returns the new workspace size in
+    bytes (the context is unbound until vl_bind)."""
+    ws = C.c_size_t(0)
+    _check(lib().vl_resize_cells(ctx, int(sim), int(max_cells), C.byref(ws)), "vl_resize_cells")
+    return int(ws.value)
 
 
 def vl_finalize(ctx, dt):
@@ -482,6 +491,28 @@ class Context:
         self.cells[k] = DeviceCells(*ts)
         self._autograd_params = None
         return n_out
+
+    def resize_cells(self, k: int, max_cells: int) -> None:
+        """Change simulation k's cell capacity (vl_resize_cells): a workspace
+        of the new size is allocated and bound with the same field, whose
+        values stay, and every simulation's current cells are uploaded again
+        (the step graphs and any tuned options' graphs are rebuilt)."""
+        torch = self.torch
+        if self.n_cells(k) > max_cells:
+            raise ValueError(f"simulation {k} holds {self.n_cells(k)} cells, more than {max_cells}")
+        nb = vl_resize_cells(self.h, k, max_cells)
+        ws = torch.zeros(max(nb, 1), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        vl_bind(self.h, self.field.data_ptr(), ws.data_ptr(), self.stream.cuda_stream)
+        self.workspace, self.ws_bytes = ws, nb
+        for j, c in enumerate(self.cells):
+            if c is None or c.n == 0:
+                continue
+            if isinstance(c, DeviceCells):
+                vl_upload_cells_dev(self.h, j, c.n, c.pos.data_ptr(), c.V.data_ptr(), c.S.data_ptr(),
+                                    c.U.data_ptr(), c.rho_star.data_ptr())
+            else:
+                vl_upload_cells(self.h, j, c.pos, c.V, c.S, c.U, c.rho_star, self.sims[j].n_sub)
 
     # -- stepping and diagnostics --
     def step(self, n: int = 1) -> None:

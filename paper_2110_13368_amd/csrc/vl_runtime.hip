@@ -640,6 +640,92 @@ static void set_rates(SubDev &d, const SimHost &s, int q, double dt, int decay)
     d.fdec = decay == VL_DECAY_ONCE ? 1.0 / (1.0 + s.lam[q] * dt) : 1.0;
 }
 
+// The cell tables' sizes and bases (from each simulation's capacity) and the
+// workspace layout; run by vl_finalize and again by vl_resize_cells.
+static void layout_workspace(vl_ctx *ctx)
+{
+    const int nsubs = (int)ctx->subs.size();
+    // cells
+    ctx->cap_total = 0;
+    ctx->comp_total = 0;
+    ctx->stage_cells = 0;
+    ctx->stage_ns = 0;
+    ctx->zl_total = 0;
+    ctx->xs_total = 0;
+    for (SimHost &s : ctx->sims) {
+        s.occ_base = ctx->cap_total;
+        s.comp_base = ctx->comp_total;
+        s.ab_base = ctx->comp_total;
+        s.zl_base = -1;
+        s.xs_base = -1;
+        if (s.max_cells > 0 && ctx->precision == VL_F32) {
+            s.zl_base = ctx->zl_total;
+            ctx->zl_total += s.n[0] * s.n[1] + 1;
+            // sources can ride on the next step's x solve (either kind)
+            s.xs_base = ctx->xs_total;
+            ctx->xs_total += s.n[1] * s.n[2] + 1;
+        }
+        ctx->cap_total += s.max_cells + 1;
+        ctx->comp_total += s.max_cells * s.ns;
+        ctx->stage_cells = std::max(ctx->stage_cells, s.max_cells);
+        ctx->stage_ns = std::max(ctx->stage_ns, s.ns);
+    }
+
+    // workspace layout
+    size_t w = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = w;
+        w = round_up(w + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    ctx->o_subs = take(sizeof(SubDev) * nsubs);
+    ctx->o_coef32 = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->n_coef32 : 0);
+    ctx->o_coefh = take(ctx->precision == VL_F32 ? sizeof(double2) * ctx->n_coef32 : 0);
+    ctx->o_coef64 = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->n_coef64 : 0);
+    ctx->o_xl32 = take(ctx->precision == VL_F32 ? sizeof(float) * ctx->n_xl32 : 0);
+    ctx->o_xl64 = take(ctx->precision == VL_F32 ? sizeof(double) * ctx->n_xl32 : 0);
+    ctx->o_itable = take(sizeof(int) * ctx->itable.size());
+    ctx->o_lltable = take(sizeof(long long) * ctx->lltable.size());
+    ctx->o_faces = take(sizeof(int4) * ctx->faces.size());
+    ctx->o_cells = take(sizeof(vl::SimCells) * ctx->n_sims);
+    ctx->o_occ_prefix = take(sizeof(int) * (ctx->n_sims + 1));
+    ctx->o_occ_vox = take(sizeof(int) * ctx->cap_total);
+    ctx->o_seg_start = take(sizeof(int) * ctx->cap_total);
+    ctx->o_comp = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->comp_total : 0);
+    ctx->o_ab = take(sizeof(double2) * ctx->comp_total);
+    // per sorted cell (FP32 path, for the adjoint): k, k rho*, upload index;
+    // and the occupied voxels in voxel order
+    const bool adj = ctx->precision == VL_F32;
+    ctx->o_krs = take(adj ? sizeof(double) * ctx->comp_total : 0);
+    ctx->o_kcell = take(adj ? sizeof(double) * ctx->cap_total : 0);
+    ctx->o_cell_of = take(adj ? sizeof(int) * ctx->cap_total : 0);
+    ctx->o_occ_vox_v = take(adj ? sizeof(int) * ctx->cap_total : 0);
+    ctx->o_pos = take(sizeof(double) * 3 * ctx->stage_cells);
+    ctx->o_V = take(sizeof(double) * ctx->stage_cells);
+    ctx->o_S = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
+    ctx->o_U = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
+    ctx->o_RS = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
+    ctx->o_keys = take(sizeof(unsigned long long) * ctx->stage_cells);
+    ctx->o_keys_alt = take(sizeof(unsigned long long) * ctx->stage_cells);
+    ctx->o_rs_hist = take(sizeof(unsigned) * (size_t)vl::radix_hist_entries(ctx->stage_cells));
+    ctx->o_seg_id = take(sizeof(int) * ctx->stage_cells);
+    ctx->o_counters = take(sizeof(int) * 8);
+    ctx->o_mass_part = take(sizeof(double) * vl::kMassBlocks);
+    ctx->o_mass_out = take(sizeof(double) * ctx->max_ns);
+    ctx->o_count = take(sizeof(unsigned long long));
+    const bool zorder = ctx->precision == VL_F32;
+    ctx->o_zkeys = take(zorder ? sizeof(unsigned long long) * ctx->stage_cells : 0);
+    ctx->o_zkeys_alt = take(zorder ? sizeof(unsigned long long) * ctx->stage_cells : 0);
+    ctx->o_occ_tmp = take(zorder ? sizeof(int) * (ctx->stage_cells + 1) : 0);
+    ctx->o_pos_idx = take(zorder ? sizeof(int) * ctx->stage_cells : 0);
+    ctx->o_line_start = take(sizeof(int) * ctx->zl_total);
+    ctx->o_xline_start = take(sizeof(int) * ctx->xs_total);
+    ctx->o_comp_v = take(zorder ? sizeof(float2) * ctx->comp_total : 0);
+    ctx->o_qcounters = take(sizeof(unsigned) * (2 + 3 * (size_t)nsubs));
+    ctx->o_qerror = take(sizeof(int));
+    ctx->ws_bytes = w;
+}
+
 int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_bytes)
 {
     if (int rc = check_ctx(ctx)) return rc;
@@ -930,88 +1016,29 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
     ctx->lltable.insert(ctx->lltable.end(), fpre.begin(), fpre.end());
     if (ctx->faces.empty()) ctx->faces.push_back(make_int4(0, 0, 0, 0));
 
-    // cells
-    ctx->cap_total = 0;
-    ctx->comp_total = 0;
-    ctx->stage_cells = 0;
-    ctx->stage_ns = 0;
-    ctx->zl_total = 0;
-    ctx->xs_total = 0;
-    for (SimHost &s : ctx->sims) {
-        s.occ_base = ctx->cap_total;
-        s.comp_base = ctx->comp_total;
-        s.ab_base = ctx->comp_total;
-        s.zl_base = -1;
-        s.xs_base = -1;
-        if (s.max_cells > 0 && ctx->precision == VL_F32) {
-            s.zl_base = ctx->zl_total;
-            ctx->zl_total += s.n[0] * s.n[1] + 1;
-            // sources can ride on the next step's x solve (either kind)
-            s.xs_base = ctx->xs_total;
-            ctx->xs_total += s.n[1] * s.n[2] + 1;
-        }
-        ctx->cap_total += s.max_cells + 1;
-        ctx->comp_total += s.max_cells * s.ns;
-        ctx->stage_cells = std::max(ctx->stage_cells, s.max_cells);
-        ctx->stage_ns = std::max(ctx->stage_ns, s.ns);
-    }
-
-    // workspace layout
-    size_t w = 0;
-    auto take = [&](size_t bytes) {
-        const size_t o = w;
-        w = round_up(w + std::max<size_t>(bytes, 1), 256);
-        return o;
-    };
-    ctx->o_subs = take(sizeof(SubDev) * nsubs);
-    ctx->o_coef32 = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->n_coef32 : 0);
-    ctx->o_coefh = take(ctx->precision == VL_F32 ? sizeof(double2) * ctx->n_coef32 : 0);
-    ctx->o_coef64 = take(ctx->precision == VL_F64 ? sizeof(double2) * ctx->n_coef64 : 0);
-    ctx->o_xl32 = take(ctx->precision == VL_F32 ? sizeof(float) * ctx->n_xl32 : 0);
-    ctx->o_xl64 = take(ctx->precision == VL_F32 ? sizeof(double) * ctx->n_xl32 : 0);
-    ctx->o_itable = take(sizeof(int) * ctx->itable.size());
-    ctx->o_lltable = take(sizeof(long long) * ctx->lltable.size());
-    ctx->o_faces = take(sizeof(int4) * ctx->faces.size());
-    ctx->o_cells = take(sizeof(vl::SimCells) * ctx->n_sims);
-    ctx->o_occ_prefix = take(sizeof(int) * (ctx->n_sims + 1));
-    ctx->o_occ_vox = take(sizeof(int) * ctx->cap_total);
-    ctx->o_seg_start = take(sizeof(int) * ctx->cap_total);
-    ctx->o_comp = take(ctx->precision == VL_F32 ? sizeof(float2) * ctx->comp_total : 0);
-    ctx->o_ab = take(sizeof(double2) * ctx->comp_total);
-    // per sorted cell (FP32 path, for the adjoint): k, k rho*, upload index;
-    // and the occupied voxels in voxel order
-    const bool adj = ctx->precision == VL_F32;
-    ctx->o_krs = take(adj ? sizeof(double) * ctx->comp_total : 0);
-    ctx->o_kcell = take(adj ? sizeof(double) * ctx->cap_total : 0);
-    ctx->o_cell_of = take(adj ? sizeof(int) * ctx->cap_total : 0);
-    ctx->o_occ_vox_v = take(adj ? sizeof(int) * ctx->cap_total : 0);
-    ctx->o_pos = take(sizeof(double) * 3 * ctx->stage_cells);
-    ctx->o_V = take(sizeof(double) * ctx->stage_cells);
-    ctx->o_S = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
-    ctx->o_U = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
-    ctx->o_RS = take(sizeof(double) * ctx->stage_cells * ctx->stage_ns);
-    ctx->o_keys = take(sizeof(unsigned long long) * ctx->stage_cells);
-    ctx->o_keys_alt = take(sizeof(unsigned long long) * ctx->stage_cells);
-    ctx->o_rs_hist = take(sizeof(unsigned) * (size_t)vl::radix_hist_entries(ctx->stage_cells));
-    ctx->o_seg_id = take(sizeof(int) * ctx->stage_cells);
-    ctx->o_counters = take(sizeof(int) * 8);
-    ctx->o_mass_part = take(sizeof(double) * vl::kMassBlocks);
-    ctx->o_mass_out = take(sizeof(double) * ctx->max_ns);
-    ctx->o_count = take(sizeof(unsigned long long));
-    const bool zorder = ctx->precision == VL_F32;
-    ctx->o_zkeys = take(zorder ? sizeof(unsigned long long) * ctx->stage_cells : 0);
-    ctx->o_zkeys_alt = take(zorder ? sizeof(unsigned long long) * ctx->stage_cells : 0);
-    ctx->o_occ_tmp = take(zorder ? sizeof(int) * (ctx->stage_cells + 1) : 0);
-    ctx->o_pos_idx = take(zorder ? sizeof(int) * ctx->stage_cells : 0);
-    ctx->o_line_start = take(sizeof(int) * ctx->zl_total);
-    ctx->o_xline_start = take(sizeof(int) * ctx->xs_total);
-    ctx->o_comp_v = take(zorder ? sizeof(float2) * ctx->comp_total : 0);
-    ctx->o_qcounters = take(sizeof(unsigned) * (2 + 3 * (size_t)nsubs));
-    ctx->o_qerror = take(sizeof(int));
-    ctx->ws_bytes = w;
+    layout_workspace(ctx);
 
     ctx->finalized = true;
     if (field_elems) *field_elems = ctx->field_elems;
+    if (workspace_bytes) *workspace_bytes = ctx->ws_bytes;
+    return VL_OK;
+}
+
+int vl_resize_cells(vl_ctx *ctx, int sim, int max_cells, size_t *workspace_bytes)
+{
+    if (int rc = check_sim(ctx, sim)) return rc;
+    if (!ctx->finalized) return fail(VL_E_STATE, "before vl_finalize, vl_reserve_cells sets the capacity");
+    if (max_cells < 0 || max_cells > (1 << 24)) return fail(VL_E_ARG, "max_cells must be in [0, 2^24]");
+    if (ctx->snap_pending) return fail(VL_E_STATE, "a snapshot is in flight: call vl_snapshot_wait first");
+    if (ctx->profiling && !ctx->recs.empty())
+        if (int rc = collect_events(ctx)) return rc;
+    if (ctx->bound && ctx->stream) VL_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->bound && !ctx->stream) VL_HIP(hipDeviceSynchronize());
+    drop_graph(ctx);
+    ctx->sims[sim].max_cells = max_cells;
+    layout_workspace(ctx);
+    ctx->bound = false;
+    ctx->ws = nullptr;
     if (workspace_bytes) *workspace_bytes = ctx->ws_bytes;
     return VL_OK;
 }

@@ -67,6 +67,7 @@ def test_setup_validation_and_sizes():
         assert _code(vb.vl_reserve_cells, h, 0, -1) == vb.VL_E_ARG
         assert _code(vb.vl_reserve_cells, h, 0, (1 << 24) + 1) == vb.VL_E_ARG
         vb.vl_reserve_cells(h, 0, 1000)
+        assert _code(vb.vl_resize_cells, h, 0, 10) == vb.VL_E_STATE  # before vl_finalize
         assert _code(vb.vl_finalize, h, 0.0) == vb.VL_E_ARG
         assert _code(vb.vl_step, h, 1) == vb.VL_E_STATE
         assert _code(vb.vl_bind, h, 0, 0, 0) == vb.VL_E_STATE  # not finalized
@@ -78,6 +79,15 @@ def test_setup_validation_and_sizes():
         assert vb.vl_field_offset(h, 1) == 2 * vol0
         assert vb.vl_volume_stride(h, 0) == vol0
         assert wb > 0 and wb % 256 == 0
+        # capacity changed after vl_finalize: the workspace grows and shrinks
+        # with it, the field layout does not move
+        wb2 = vb.vl_resize_cells(h, 0, 50_000)
+        assert wb2 > wb and wb2 % 256 == 0
+        assert vb.vl_resize_cells(h, 0, 1000) == wb
+        assert _code(vb.vl_resize_cells, h, 0, -1) == vb.VL_E_ARG
+        assert _code(vb.vl_resize_cells, h, 0, (1 << 24) + 1) == vb.VL_E_ARG
+        assert _code(vb.vl_resize_cells, h, 2, 10) == vb.VL_E_ARG  # no such simulation
+        assert vb.vl_field_offset(h, 1) == 2 * vol0
         assert _code(vb.vl_finalize, h, 0.01) == vb.VL_E_STATE
         assert _code(vb.vl_set_grid, h, 0, 4, 4, 4, 1, 1, 1, 0, 0, 0) == vb.VL_E_STATE
         assert _code(vb.vl_bind, h, 0, 0, 0) == vb.VL_E_ARG  # null buffers

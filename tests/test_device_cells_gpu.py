@@ -189,3 +189,42 @@ def test_cell_counts_change_by_orders_of_magnitude():
                              f"mode {mode}, {len(idx)} cells")
         finally:
             ctx.close()
+
+
+@pytest.mark.parametrize("sources", [1, 2])
+def test_capacity_grows_without_refinalising(sources):
+    """vl_resize_cells: a simulation set up for 30 cells takes 3000 after a
+    resize and a new bind, with no new context.  The field survives the
+    rebind bitwise, the other simulation of the batch keeps its cells, and
+    the fields before and after match the oracle given the same uploads."""
+    import copy
+    full = _spec((60, 14, 11), 2, "mixed", 3000, 7)
+    other = _spec((33, 20, 17), 1, "neumann", 150, 8)
+    c = full.cells
+    idx = np.sort(np.random.default_rng(12).choice(c.n, size=30, replace=False))
+    few = copy.copy(full)
+    few.cells = W.Cells(pos=c.pos[idx], V=c.V[idx], S=c.S[idx], U=c.U[idx], rho_star=c.rho_star[idx])
+    oa, ob = O.from_spec(few), O.from_spec(other)
+    ctx = vb.Context([few, other], device="cuda:0")
+    try:
+        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, sources)
+        ctx.step(3)
+        oa.step(3)
+        ob.step(3)
+        before = [ctx.get_field(k).copy() for k in range(2)]
+        with pytest.raises(vb.VoxlodError) as e:
+            ctx.upload_cells(0, c)
+        assert e.value.code == vb.VL_E_SHAPE
+        ctx.resize_cells(0, 3000)
+        assert all(np.array_equal(before[k], ctx.get_field(k)) for k in range(2)), "field changed by the rebind"
+        assert ctx.n_cells(1) == 150
+        assert ctx.get_option(vb.VL_OPT_FUSE_SOURCES) == sources
+        n_out = ctx.upload_cells(0, c)
+        assert n_out == oa.upload_cells(c.pos, c.V, c.S, c.U, c.rho_star)
+        ctx.step(4)
+        oa.step(4)
+        ob.step(4)
+        assert_close(ctx.get_field(0).astype(np.float64), oa.get_field(), 1e-5, f"grown sim, sources {sources}")
+        assert_close(ctx.get_field(1).astype(np.float64), ob.get_field(), 1e-5, f"other sim, sources {sources}")
+    finally:
+        ctx.close()
