@@ -29,9 +29,20 @@
 // per 32 columns for lines of up to 65 voxels), loaded
 // with lanes along x and read back with lanes along the lines.  The half line
 // a lane owns stays in VGPRs (CAP values).
+#include <climits>
+
 #include "vl_device.h"
 
 namespace vl {
+
+// z tiles apply their cells' sources while they store, from a stage of up to
+// kZSrcStage occupied voxels, in the classes of up to kZSrcMaxCap values per
+// lane: lines that short leave L2 before a pass after the stores could
+// re-read them (on the 256-grid batch that pass read 1.46x the field; the
+// 100-value class on a 128 MB field, which the Infinity Cache holds, was
+// faster with the pass after the stores)
+constexpr int kZSrcStage = 1024;
+constexpr int kZSrcMaxCap = 64;
 
 
 // One tile of one sweep: 64 lines of volume S, tile index `local` within the
@@ -347,6 +358,52 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
         v[0] = face_value(S.dval32, f_last);
     }
 
+    // ---- cell sources of this tile's z-lines, applied as it stores (the
+    //      classes up to kZSrcMaxCap values; a tile with more than
+    //      kZSrcStage occupied voxels, and the longer classes, apply them
+    //      after their stores instead) ----
+    // The occupied voxels of the tile's 64 z-lines are one run of the
+    // z-line-ordered list, sorted by (line, k) within it.  Staged in LDS,
+    // each lane walks its own line's entries upwards (top wave: rows 0 ..
+    // m - 1, then the middle row) or downwards (bottom wave: rows n - 1 ..
+    // m + 1) while it stores its rows, and stores rho R + P where the row
+    // matches: the same fmaf on the same FP32 value as the pass after the
+    // stores.
+    [[maybe_unused]] bool src_walk = false;  // uniform
+    [[maybe_unused]] int zp = 0, zk = 0, za = 0, zb = 0;  // this lane's walk: position, its row, range [za, zb)
+    [[maybe_unused]] const int *zs = nullptr;       // the staged entries' rows
+    [[maybe_unused]] const float2 *zc = nullptr;    // and their composites (P, R)
+    if constexpr (AXIS == 2 && CAP <= kZSrcMaxCap) {
+        __shared__ int zs_k[kZSrcStage];
+        __shared__ float2 zs_c[kZSrcStage];
+        if (src.enabled) {
+            const SimCells &C = src.cells[S.sim];
+            if (C.zl_base >= 0 && !(src.skip_carried && C.xs_base >= 0)) {
+                const int nxy = nx * ny;
+                const int L0 = local * kTileLines;
+                const int *ls = src.line_start + C.zl_base;
+                const int e0 = ls[L0], e1 = ls[min(L0 + kTileLines, nxy)];
+                if (e1 - e0 <= kZSrcStage) {
+                    for (int e = e0 + (int)threadIdx.x; e < e1; e += 2 * kWave) {
+                        zs_k[e - e0] = src.occ_vox[C.occ_base + e] / nxy;
+                        zs_c[e - e0] = src.comp[C.comp_base + (size_t)e * C.ns + S.sub];
+                    }
+                    __syncthreads();
+                    // this lane's line (past the volume's last line: a copy of
+                    // it, which then stores the same values)
+                    const int L = min(L0 + lane, nxy - 1);
+                    za = ls[L] - e0;
+                    zb = ls[L + 1] - e0;
+                    zp = top ? za : zb - 1;
+                    zk = top ? (zp < zb ? zs_k[zp] : INT_MAX) : (zp >= za ? zs_k[zp] : -1);
+                    zs = zs_k;
+                    zc = zs_c;
+                    src_walk = true;
+                }
+            }
+        }
+    }
+
     // ---- store ----
     if (AXIS == 0 && XWide<CAP>::value) {
         if (top && line_ok) bstore(rs, lane_b + (unsigned)m * 4u, 0, xm32);
@@ -378,13 +435,51 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
             }
         }
     } else {
-        if (top) bstore_p<kPol>(rs, lane_b, m * row_b, xm32);
-        const int row0 = top ? 0 : (n - 1) * row_b;
-        const int step = top ? row_b : -row_b;
-        VL_FOR_UP(CAP, nel, t, bstore_p<kPol>(rs, lane_b, row0 + t * step, v[t]);)
+        bool stored = false;
+        if constexpr (AXIS == 2 && CAP <= kZSrcMaxCap) {
+            if (src_walk) {  // uniform
+                const int row0 = top ? 0 : (n - 1) * row_b;
+                const int step = top ? row_b : -row_b;
+                if (top) {
+                    VL_FOR_UP(CAP, nel, t, {
+                        float val = v[t];
+                        if (t == zk) {
+                            const float2 q = zc[zp];
+                            val = fmaf(val, q.y, q.x);
+                            ++zp;
+                            zk = zp < zb ? zs[zp] : INT_MAX;
+                        }
+                        bstore_p<kPol>(rs, lane_b, row0 + t * step, val);
+                    })
+                    if (zk == m) {
+                        const float2 q = zc[zp];
+                        xm32 = fmaf(xm32, q.y, q.x);
+                    }
+                    bstore_p<kPol>(rs, lane_b, m * row_b, xm32);
+                } else {
+                    VL_FOR_UP(CAP, nel, t, {
+                        float val = v[t];
+                        if (n - 1 - t == zk) {
+                            const float2 q = zc[zp];
+                            val = fmaf(val, q.y, q.x);
+                            --zp;
+                            zk = zp >= za ? zs[zp] : -1;
+                        }
+                        bstore_p<kPol>(rs, lane_b, row0 + t * step, val);
+                    })
+                }
+                stored = true;
+            }
+        }
+        if (!stored) {
+            if (top) bstore_p<kPol>(rs, lane_b, m * row_b, xm32);
+            const int row0 = top ? 0 : (n - 1) * row_b;
+            const int step = top ? row_b : -row_b;
+            VL_FOR_UP(CAP, nel, t, bstore_p<kPol>(rs, lane_b, row0 + t * step, v[t]);)
+        }
 
         // ---- cell sources of this tile's z-lines (after the last P_D) ----
-        if (AXIS == 2 && src.enabled) {
+        if (AXIS == 2 && src.enabled && !(CAP <= kZSrcMaxCap && src_walk)) {
             const SimCells &C = src.cells[S.sim];
             if (C.zl_base >= 0 && !(src.skip_carried && C.xs_base >= 0)) {
                 const int nlines = nx * ny;
