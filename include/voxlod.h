@@ -362,6 +362,14 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * change, and vl_adjoint returns VL_E_STATE while any simulation holds cells
  * uploaded without them.  It applies to the uploads that follow. */
 #define VL_OPT_ADJOINT_TABLES 9
+/* VL_OPT_Z_SOURCES_STORING (FP32 path, default -1): where the z sweep of
+ * lines of up to 129 voxels applies the cell sources when they are applied
+ * in the z sweep: 1 while each tile stores its rows (its occupied voxels
+ * staged in LDS, up to 1024 per tile), 0 in a pass over them after the
+ * tile's stores, -1 (auto) the first when the field is larger than the 256
+ * MB Infinity Cache, where that pass would re-read lines from HBM.  Fields
+ * are bitwise the same either way. */
+#define VL_OPT_Z_SOURCES_STORING 10
 /* Launch-shape options (no passage of the paper defines them; fields do not
  * depend on them beyond rounding, and the placements of the sources and the
  * x+y-per-plane option give bitwise equal fields).  Unknown options and

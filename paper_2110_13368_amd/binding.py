@@ -32,6 +32,7 @@ VL_OPT_FUSE_XY = 6
 VL_OPT_X_LANES = 7
 VL_OPT_X_LANE_LINES = 8
 VL_OPT_ADJOINT_TABLES = 9
+VL_OPT_Z_SOURCES_STORING = 10
 VL_K_SWEEP_X, VL_K_SWEEP_Y, VL_K_SWEEP_Z, VL_K_SOURCES, VL_K_DIRICHLET, VL_K_DECAY, VL_K_STEP = range(7)
 KERNEL_NAMES = ["sweep_x", "sweep_y", "sweep_z", "sources", "dirichlet", "decay", "step",
                 "replay_x", "replay_y", "replay_z", "adjoint_x", "adjoint_y", "adjoint_z",

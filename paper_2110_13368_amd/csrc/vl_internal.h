@@ -114,6 +114,7 @@ struct FusedSources {
     const float2 *comp;
     int enabled;
     int skip_carried;  // leave simulations with xs_base >= 0 to the next x solve
+    int while_storing;  // short-line z tiles apply them as they store (else in a pass after)
 };
 
 // Cell sources of the previous step applied by the x solve (lanes along the

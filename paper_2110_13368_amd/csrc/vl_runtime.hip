@@ -138,6 +138,7 @@ struct vl_ctx {
     size_t xy_lds_max = 0;
     bool xcd_order = true;
     bool adj_tables = true;  // uploads write the per-cell tables of the adjoint
+    int z_src_store = -1;    // VL_OPT_Z_SOURCES_STORING: -1 auto, 0 off, 1 on
 
     // one-launch step (FP32): queue over all tiles of the three sweeps
     int step_mode = VL_MODE_LAUNCHES;
@@ -316,6 +317,17 @@ std::vector<int> cells_plan(const vl_ctx *ctx)
     return p;
 }
 
+// Whether the z sweep's short-line tiles apply their cells' sources while
+// they store rather than in a pass after their stores.  That pass re-reads
+// the occupied voxels' lines, which costs HBM traffic once they have left
+// the caches; on a field that the 256 MB Infinity Cache holds it is cheaper
+// than the walk.  Auto: on when the field is larger than that cache.
+bool z_while_storing(const vl_ctx *ctx)
+{
+    if (ctx->z_src_store >= 0) return ctx->z_src_store == 1;
+    return (double)ctx->field_elems * (double)ctx->esize > 256.0 * 1024 * 1024;
+}
+
 // phase: kStepWhole a complete step; with carried sources kStepCarryFirst
 // (the z sweep leaves eligible simulations' sources to the next x solve) and
 // kStepCarry (the x solve also applies the previous step's).
@@ -334,7 +346,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
         const bool fused = ctx->fuse_sources >= 1 && total_occ > 0;
         const vl::FusedSources src{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
                                    ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), fused ? 1 : 0,
-                                   phase != kStepWhole ? 1 : 0};
+                                   phase != kStepWhole ? 1 : 0, z_while_storing(ctx) ? 1 : 0};
         const vl::CarriedSources carry{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_xline_start),
                                        ctx->at<int>(ctx->o_occ_vox_v), ctx->at<float2>(ctx->o_comp_v),
                                        phase == kStepCarry ? 1 : 0};
@@ -1526,6 +1538,13 @@ int vl_set_option(vl_ctx *ctx, int option, int value)
         ctx->xcd_order = value == 1;
         return VL_OK;
     }
+    if (option == VL_OPT_Z_SOURCES_STORING) {
+        if (value < -1 || value > 1) return fail(VL_E_ARG, "VL_OPT_Z_SOURCES_STORING takes -1, 0 or 1");
+        const bool before = z_while_storing(ctx);
+        ctx->z_src_store = value;
+        if (z_while_storing(ctx) != before) drop_graph(ctx);
+        return VL_OK;
+    }
     if (option == VL_OPT_ADJOINT_TABLES) {
         if (value != 0 && value != 1) return fail(VL_E_ARG, "VL_OPT_ADJOINT_TABLES takes 0 or 1");
         ctx->adj_tables = value == 1;
@@ -1554,6 +1573,7 @@ int vl_get_option(vl_ctx *ctx, int option, int *value)
     case VL_OPT_X_LANES: *value = ctx->x_lanes; return VL_OK;
     case VL_OPT_X_LANE_LINES: *value = ctx->xl_lpw; return VL_OK;
     case VL_OPT_ADJOINT_TABLES: *value = ctx->adj_tables ? 1 : 0; return VL_OK;
+    case VL_OPT_Z_SOURCES_STORING: *value = ctx->z_src_store; return VL_OK;
     default: return fail(VL_E_ARG, "unknown option");
     }
 }
@@ -1825,7 +1845,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
     const double2 *coef = ctx->at<double2>(ctx->o_coefh);
     float *field = (float *)ctx->field;
     const vl::FusedSources nosrc{ctx->at<vl::SimCells>(ctx->o_cells), ctx->at<int>(ctx->o_line_start),
-                                 ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0, 0};
+                                 ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp), 0, 0, 0};
     // x: the lanes-along-the-line solve for long lines when selected, the
     // split sweeps otherwise; then y and z
     std::vector<std::pair<const Launch *, bool>> order;  // (launch, lanes along the line)

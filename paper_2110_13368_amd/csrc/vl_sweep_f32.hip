@@ -376,7 +376,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     if constexpr (AXIS == 2 && CAP <= kZSrcMaxCap) {
         __shared__ int zs_k[kZSrcStage];
         __shared__ float2 zs_c[kZSrcStage];
-        if (src.enabled) {
+        if (src.enabled && src.while_storing) {
             const SimCells &C = src.cells[S.sim];
             if (C.zl_base >= 0 && !(src.skip_carried && C.xs_base >= 0)) {
                 const int nxy = nx * ny;

@@ -132,6 +132,10 @@ def test_options_on_the_host():
         vb.vl_set_option(h, vb.VL_OPT_ADJOINT_TABLES, 0)
         assert vb.vl_get_option(h, vb.VL_OPT_ADJOINT_TABLES) == 0
         assert _code(vb.vl_set_option, h, vb.VL_OPT_ADJOINT_TABLES, 2) == vb.VL_E_ARG
+        assert vb.vl_get_option(h, vb.VL_OPT_Z_SOURCES_STORING) == -1
+        vb.vl_set_option(h, vb.VL_OPT_Z_SOURCES_STORING, 1)
+        assert vb.vl_get_option(h, vb.VL_OPT_Z_SOURCES_STORING) == 1
+        assert _code(vb.vl_set_option, h, vb.VL_OPT_Z_SOURCES_STORING, 2) == vb.VL_E_ARG
         vb.vl_set_option(h, vb.VL_OPT_X_LANES, 2)  # lines of 65 voxels and more
         assert vb.vl_get_option(h, vb.VL_OPT_X_LANES) == 2
         assert _code(vb.vl_set_option, h, vb.VL_OPT_X_LANES, 3) == vb.VL_E_ARG

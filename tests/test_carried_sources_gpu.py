@@ -155,3 +155,41 @@ def test_hundreds_of_fast_cells_in_one_voxel(x_lanes):
     for mode, f in fields.items():
         assert np.array_equal(f, ref), mode
     assert_close(ref, run_oracle(spec, 6), 1e-5, "500 fast cells in two voxels")
+
+
+def _run_z_storing(specs, steps, storing, sources_mode):
+    ctx = vb.Context(specs, device="cuda:0")
+    try:
+        ctx.set_option(vb.VL_OPT_X_LANES, 1)
+        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, sources_mode)
+        ctx.set_option(vb.VL_OPT_Z_SOURCES_STORING, storing)
+        assert ctx.get_option(vb.VL_OPT_Z_SOURCES_STORING) == storing
+        ctx.step(steps)
+        ctx.sync()
+        return [ctx.get_field(k).astype(np.float64) for k in range(len(specs))]
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_z_sources_while_storing_equal_after_stores(steps):
+    """Short z-lines (up to 129 voxels) apply the sources while each tile
+    stores (VL_OPT_Z_SOURCES_STORING 1) or in a pass after its stores (0):
+    bitwise equal, and equal to the sources carried into the next x solve.
+    The cases: the batch above (z-lines of 3 to 11 voxels), z-lines of 100
+    voxels with a few hundred occupied voxels per tile (the 64-value class),
+    and one whose tiles hold more than the 1024 occupied voxels the stage
+    takes (those tiles use the pass after the stores), with two cells in
+    some voxels."""
+    specs = _batch()
+    specs.append(_spec((24, 20, 100), 2, "mixed", 3000, 8))
+    dense = _spec((16, 16, 100), 1, "neumann", 30000, 9)
+    dense.cells.pos[1::5] = dense.cells.pos[0::5][: len(dense.cells.pos[1::5])]
+    specs.append(dense)
+    on = _run_z_storing(specs, steps, 1, 1)
+    off = _run_z_storing(specs, steps, 0, 1)
+    carried = _run_z_storing(specs, steps, -1, 2)
+    for k in range(len(specs)):
+        assert np.array_equal(on[k], off[k]), f"sim {k}: while storing vs after the stores"
+        assert np.array_equal(on[k], carried[k]), f"sim {k}: in z vs carried into x"
+        assert_close(on[k], run_oracle(specs[k], steps), 1e-5, f"z sources while storing, sim {k}")
