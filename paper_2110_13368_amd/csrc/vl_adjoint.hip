@@ -356,7 +356,7 @@ hipError_t launch_sources_adjoint(const SimCells *cells, int nsims, const int *o
                                   const int *cell_out_base, double *dS, double *dU, hipStream_t st)
 {
     if (occ_bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_adjoint_kernel, dim3((occ_bound + 127) / 128, max_ns), dim3(128), 0, st, cells,
+    hipLaunchKernelGGL(sources_adjoint_kernel, dim3((unsigned)((occ_bound + 127LL) / 128), max_ns), dim3(128), 0, st, cells,
                        nsims, occ_prefix, occ_bound, subs, occ_vox_v, seg_start, ab, krs, kcell, cell_of, rho, w,
                        cell_out_base, dS, dU);
     return hipGetLastError();

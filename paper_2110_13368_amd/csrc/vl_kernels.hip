@@ -781,7 +781,7 @@ hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *
                                    float *field, int skip_carried, hipStream_t st)
 {
     if (occ_bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_thin_f32_kernel, dim3((occ_bound + 255) / 256, max_ns), dim3(256), 0, st,
+    hipLaunchKernelGGL(sources_thin_f32_kernel, dim3((unsigned)((occ_bound + 255LL) / 256), max_ns), dim3(256), 0, st,
                        cells, nsims, occ_prefix, occ_bound, subs, occ_vox, comp, field, skip_carried);
     return hipGetLastError();
 }
@@ -791,7 +791,7 @@ hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_p
                               float *field, int only_carried, hipStream_t st)
 {
     if (occ_bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_f32_kernel, dim3((occ_bound + 255) / 256, max_ns), dim3(256), 0, st,
+    hipLaunchKernelGGL(sources_f32_kernel, dim3((unsigned)((occ_bound + 255LL) / 256), max_ns), dim3(256), 0, st,
                        cells, nsims, occ_prefix, occ_bound, subs, occ_vox, comp, field, only_carried);
     return hipGetLastError();
 }
@@ -827,7 +827,7 @@ hipError_t launch_sources_plain(const SimCells *cells, int nsims, const int *occ
                                 const double2 *ab, double *field, hipStream_t st)
 {
     if (occ_bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sources_plain_kernel, dim3((occ_bound + 255) / 256), dim3(256), 0, st, cells,
+    hipLaunchKernelGGL(sources_plain_kernel, dim3((unsigned)((occ_bound + 255LL) / 256)), dim3(256), 0, st, cells,
                        nsims, occ_prefix, occ_bound, subs, occ_vox, seg_start, ab, field);
     return hipGetLastError();
 }
