@@ -541,16 +541,17 @@ hipError_t launch_segments(const unsigned long long *keys, int n_cap, int n, int
 
 // FP32 path: occupied voxels re-ordered by z-line (i, j) then k, so that the
 // voxels of 64 consecutive z-lines form one contiguous range.  Keys are
-// ((line * nz + k) << 32) | (index in voxel order).  The number of occupied
-// voxels is counts[1] (on the device), at most n_cap.
+// (line << 32) | (index in voxel order), sorted stably on the line bits.  The
+// number of occupied voxels is counts[1] (on the device), at most n_cap.
 __global__ void zline_keys_kernel(const int *__restrict__ occ_vox_v, const int *__restrict__ counts, int n_cap,
                                   int nxy, int nz, unsigned long long *__restrict__ zkeys)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_cap || p >= counts[1]) return;
+    // the list is in voxel order, i.e. by (k, line): a stable sort on the
+    // line alone leaves each line's voxels in k order
     const int v = occ_vox_v[p];
-    const unsigned long long line = (unsigned)(v % nxy), k = (unsigned)(v / nxy);
-    zkeys[p] = ((line * (unsigned long long)nz + k) << 32) | (unsigned)p;
+    zkeys[p] = ((unsigned long long)(unsigned)(v % nxy) << 32) | (unsigned)p;
 }
 
 // After sorting the z keys: pos[voxel-order index] = z-order index, the
@@ -568,8 +569,8 @@ __global__ void zline_scatter_kernel(const unsigned long long *__restrict__ zkey
     const int q = (int)(key & 0xffffffffull);
     pos[q] = p;
     occ_vox[p] = occ_vox_v[q];
-    const int L = (int)((key >> 32) / (unsigned long long)nz);
-    const int Lprev = (p == 0) ? -1 : (int)((zkeys[p - 1] >> 32) / (unsigned long long)nz);
+    const int L = (int)(key >> 32);
+    const int Lprev = (p == 0) ? -1 : (int)(zkeys[p - 1] >> 32);
     for (int l = Lprev + 1; l <= L; ++l) line_start[l] = p;
     if (p == n_occ - 1)
         for (int l = L + 1; l <= nxy; ++l) line_start[l] = n_occ;
@@ -592,9 +593,8 @@ hipError_t launch_zline_order(const int *occ_vox_v, const int *counts, int n_cap
     if (n_cap <= 0) return hipSuccess;
     const dim3 grid((n_cap + 255) / 256), block(256);
     hipLaunchKernelGGL(zline_keys_kernel, grid, block, 0, st, occ_vox_v, counts, n_cap, nxy, nz, zkeys);
-    // the z-line part of a key is below nxy * nz
-    hipError_t e = launch_radix_sort(zkeys, zalt, n_cap, counts + 1, 32,
-                                     bit_length((unsigned long long)nxy * (unsigned long long)nz), hist, st);
+    // the line part of a key is below nxy
+    hipError_t e = launch_radix_sort(zkeys, zalt, n_cap, counts + 1, 32, bit_length((unsigned long long)nxy), hist, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zline_scatter_kernel, grid, block, 0, st, zkeys, counts, n_cap, nxy, nz, occ_vox_v, occ_vox,
                        pos, line_start);
