@@ -731,22 +731,24 @@ __device__ __forceinline__ int find_slot_i(const int *__restrict__ prefix, int c
 
 // The composite of occupied voxel jl (of simulation C) on substrate s:
 // rho <- rho R + P, one fused multiply-add (the same operation wherever the
-// sources are applied, so every placement gives the same bits).
+// sources are applied, so every placement gives the same bits), for the
+// jl-th occupied voxel in voxel order and its substrate-major composite
+// (stride occ_cap): neighbouring threads update neighbouring voxels.
 __device__ __forceinline__ void apply_composite(const SimCells &C, int jl, int s, const SubDev *__restrict__ subs,
-                                                const int *__restrict__ occ_vox, const float2 *__restrict__ comp,
+                                                const int *__restrict__ occ_vox_v, const float2 *__restrict__ comp_v,
                                                 float *__restrict__ field)
 {
-    const int v = occ_vox[C.occ_base + jl];
-    const float2 ab = comp[C.comp_base + (size_t)jl * C.ns + s];
+    const int v = occ_vox_v[C.occ_base + jl];
+    const float2 ab = comp_v[C.comp_base + (size_t)s * C.occ_cap + jl];
     float *p = field + subs[C.sub0 + s].base + v;
     *p = fmaf(*p, ab.y, ab.x);
 }
 
-// FP32: one thread per (occupied voxel, substrate).
+// FP32: one thread per (occupied voxel, substrate), the voxels in voxel order.
 __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims,
                                    const int *__restrict__ occ_prefix, int occ_bound,
-                                   const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
-                                   const float2 *__restrict__ comp, float *__restrict__ field, int only_carried)
+                                   const SubDev *__restrict__ subs, const int *__restrict__ occ_vox_v,
+                                   const float2 *__restrict__ comp_v, float *__restrict__ field, int only_carried)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
@@ -754,7 +756,7 @@ __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns || (only_carried && C.xs_base < 0)) return;
-    apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox, comp, field);
+    apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox_v, comp_v, field);
 }
 
 // The same update for the simulations one voxel thick in z, whose z solve is
@@ -764,8 +766,8 @@ __global__ void sources_f32_kernel(const SimCells *__restrict__ cells, int nsims
 // leave those whose sources the next x solve applies.
 __global__ void sources_thin_f32_kernel(const SimCells *__restrict__ cells, int nsims,
                                         const int *__restrict__ occ_prefix, int occ_bound,
-                                        const SubDev *__restrict__ subs, const int *__restrict__ occ_vox,
-                                        const float2 *__restrict__ comp, float *__restrict__ field, int skip_carried)
+                                        const SubDev *__restrict__ subs, const int *__restrict__ occ_vox_v,
+                                        const float2 *__restrict__ comp_v, float *__restrict__ field, int skip_carried)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
@@ -773,26 +775,26 @@ __global__ void sources_thin_f32_kernel(const SimCells *__restrict__ cells, int 
     const int sim = find_slot_i(occ_prefix, nsims, j);
     const SimCells &C = cells[sim];
     if (s >= C.ns || subs[C.sub0].n[2] != 1 || (skip_carried && C.xs_base >= 0)) return;
-    apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox, comp, field);
+    apply_composite(C, j - occ_prefix[sim], s, subs, occ_vox_v, comp_v, field);
 }
 
 hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
-                                   int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
+                                   int max_ns, const SubDev *subs, const int *occ_vox_v, const float2 *comp_v,
                                    float *field, int skip_carried, hipStream_t st)
 {
     if (occ_bound <= 0) return hipSuccess;
     hipLaunchKernelGGL(sources_thin_f32_kernel, dim3((unsigned)((occ_bound + 255LL) / 256), max_ns), dim3(256), 0, st,
-                       cells, nsims, occ_prefix, occ_bound, subs, occ_vox, comp, field, skip_carried);
+                       cells, nsims, occ_prefix, occ_bound, subs, occ_vox_v, comp_v, field, skip_carried);
     return hipGetLastError();
 }
 
 hipError_t launch_sources_f32(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
-                              int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
+                              int max_ns, const SubDev *subs, const int *occ_vox_v, const float2 *comp_v,
                               float *field, int only_carried, hipStream_t st)
 {
     if (occ_bound <= 0) return hipSuccess;
     hipLaunchKernelGGL(sources_f32_kernel, dim3((unsigned)((occ_bound + 255LL) / 256), max_ns), dim3(256), 0, st,
-                       cells, nsims, occ_prefix, occ_bound, subs, occ_vox, comp, field, only_carried);
+                       cells, nsims, occ_prefix, occ_bound, subs, occ_vox_v, comp_v, field, only_carried);
     return hipGetLastError();
 }
 

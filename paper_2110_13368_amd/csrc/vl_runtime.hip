@@ -22,7 +22,7 @@ hipError_t launch_check_cells(int n, int ns, const double *V, const double *S, c
 // cell sources of the simulations one voxel thick, whose z solve is not
 // launched (vl_kernels.hip)
 hipError_t launch_sources_thin_f32(const SimCells *cells, int nsims, const int *occ_prefix, int occ_bound,
-                                   int max_ns, const SubDev *subs, const int *occ_vox, const float2 *comp,
+                                   int max_ns, const SubDev *subs, const int *occ_vox_v, const float2 *comp_v,
                                    float *field, int skip_carried, hipStream_t st);
 // the adjoint's reverse x solve with the lanes along the line (vl_adjoint_xl.hip)
 hipError_t launch_adjoint_xl(int K, const SweepLaunch &L, const SubDev *subs, const float *xl32, float *w,
@@ -431,7 +431,7 @@ int enqueue_step(vl_ctx *ctx, int phase)
             rc = timed(ctx, VL_K_SOURCES, [&] {
                 return vl::launch_sources_thin_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
                                                    ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns, subs,
-                                                   ctx->at<int>(ctx->o_occ_vox), ctx->at<float2>(ctx->o_comp),
+                                                   ctx->at<int>(ctx->o_occ_vox_v), ctx->at<float2>(ctx->o_comp_v),
                                                    field, phase != kStepWhole ? 1 : 0, st);
             });
             if (rc) return rc;
@@ -441,8 +441,8 @@ int enqueue_step(vl_ctx *ctx, int phase)
             rc = timed(ctx, VL_K_SOURCES, [&] {
                 return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
                                               ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
-                                              subs, ctx->at<int>(ctx->o_occ_vox),
-                                              ctx->at<float2>(ctx->o_comp), field, 0, st);
+                                              subs, ctx->at<int>(ctx->o_occ_vox_v),
+                                              ctx->at<float2>(ctx->o_comp_v), field, 0, st);
             });
             if (rc) return rc;
         }
@@ -498,8 +498,8 @@ int enqueue_carried_sources(vl_ctx *ctx)
     return timed(ctx, VL_K_SOURCES, [&] {
         return vl::launch_sources_f32(ctx->at<vl::SimCells>(ctx->o_cells), ctx->n_sims,
                                       ctx->at<int>(ctx->o_occ_prefix), total_occ, ctx->max_ns,
-                                      ctx->at<SubDev>(ctx->o_subs), ctx->at<int>(ctx->o_occ_vox),
-                                      ctx->at<float2>(ctx->o_comp), (float *)ctx->field, 1, ctx->stream);
+                                      ctx->at<SubDev>(ctx->o_subs), ctx->at<int>(ctx->o_occ_vox_v),
+                                      ctx->at<float2>(ctx->o_comp_v), (float *)ctx->field, 1, ctx->stream);
     });
 }
 
