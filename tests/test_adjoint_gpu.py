@@ -484,3 +484,27 @@ def test_uploads_without_adjoint_tables():
         finally:
             ctx.close()
     assert np.array_equal(fields[0], fields[1])
+
+
+def test_adjoint_with_z_sources_while_storing():
+    """The adjoint's checkpointed forward and segment replays with the z
+    tiles applying the cell sources while they store (forced on; these small
+    fields leave it off by default) give bitwise the gradients of the pass
+    after the stores, and the oracle's."""
+    spec, target = _case(1401, (19, 15, 70), n_cells=300)
+    n_steps = 6
+    o, r = _oracle_grads(spec, target, O.DECAY_ONCE, n_steps)
+    got = []
+    for storing in (1, 0):
+        ctx = vb.Context([spec], device="cuda:0")
+        try:
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, 1)
+            ctx.set_option(vb.VL_OPT_Z_SOURCES_STORING, storing)
+            g = ctx.adjoint(n_steps, 2, [r.astype(np.float32)])
+            got.append({k: (v.double().cpu().numpy() if hasattr(v, "cpu") else np.asarray(v))
+                        for k, v in g[0].items()})
+        finally:
+            ctx.close()
+    for k in got[0]:
+        assert np.array_equal(got[0][k], got[1][k]), f"{k}: while storing vs after the stores"
+    _compare(got[0], o, "z sources while storing")
