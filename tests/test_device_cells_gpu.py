@@ -191,8 +191,8 @@ def test_cell_counts_change_by_orders_of_magnitude():
             ctx.close()
 
 
-@pytest.mark.parametrize("sources", [1, 2])
-def test_capacity_grows_without_refinalising(sources):
+@pytest.mark.parametrize("precision,sources", [(vb.VL_F32, 1), (vb.VL_F32, 2), (vb.VL_F64, None)])
+def test_capacity_grows_without_refinalising(precision, sources):
     """vl_resize_cells: a simulation set up for 30 cells takes 3000 after a
     resize and a new bind, with no new context.  The field survives the
     rebind bitwise, the other simulation of the batch keeps its cells, and
@@ -204,10 +204,16 @@ def test_capacity_grows_without_refinalising(sources):
     idx = np.sort(np.random.default_rng(12).choice(c.n, size=30, replace=False))
     few = copy.copy(full)
     few.cells = W.Cells(pos=c.pos[idx], V=c.V[idx], S=c.S[idx], U=c.U[idx], rho_star=c.rho_star[idx])
+    if precision == vb.VL_F64:
+        for sp in (full, other):
+            sp.rho0 = sp.rho0.astype(np.float64)
+        few.rho0 = full.rho0
     oa, ob = O.from_spec(few), O.from_spec(other)
-    ctx = vb.Context([few, other], device="cuda:0")
+    ctx = vb.Context([few, other], precision=precision, device="cuda:0")
+    tol = 1e-12 if precision == vb.VL_F64 else 1e-5
     try:
-        ctx.set_option(vb.VL_OPT_FUSE_SOURCES, sources)
+        if sources is not None:
+            ctx.set_option(vb.VL_OPT_FUSE_SOURCES, sources)
         ctx.step(3)
         oa.step(3)
         ob.step(3)
@@ -218,13 +224,14 @@ def test_capacity_grows_without_refinalising(sources):
         ctx.resize_cells(0, 3000)
         assert all(np.array_equal(before[k], ctx.get_field(k)) for k in range(2)), "field changed by the rebind"
         assert ctx.n_cells(1) == 150
-        assert ctx.get_option(vb.VL_OPT_FUSE_SOURCES) == sources
+        if sources is not None:
+            assert ctx.get_option(vb.VL_OPT_FUSE_SOURCES) == sources
         n_out = ctx.upload_cells(0, c)
         assert n_out == oa.upload_cells(c.pos, c.V, c.S, c.U, c.rho_star)
         ctx.step(4)
         oa.step(4)
         ob.step(4)
-        assert_close(ctx.get_field(0).astype(np.float64), oa.get_field(), 1e-5, f"grown sim, sources {sources}")
-        assert_close(ctx.get_field(1).astype(np.float64), ob.get_field(), 1e-5, f"other sim, sources {sources}")
+        assert_close(ctx.get_field(0).astype(np.float64), oa.get_field(), tol, f"grown sim, sources {sources}")
+        assert_close(ctx.get_field(1).astype(np.float64), ob.get_field(), tol, f"other sim, sources {sources}")
     finally:
         ctx.close()
