@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "vl_internal.h"
 
 using vl::SubDev;
@@ -52,6 +54,17 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// A roctx range over one library call: rocprofv3 --marker-trace records its
+// host-side start and end on the calling thread, so a timeline shows which
+// call enqueued which kernels.  Without a tool attached the push and pop are
+// calls into an empty dispatch table.
+struct MarkerRange {
+    explicit MarkerRange(const char *name) { roctxRangePushA(name); }
+    ~MarkerRange() { roctxRangePop(); }
+    MarkerRange(const MarkerRange &) = delete;
+    MarkerRange &operator=(const MarkerRange &) = delete;
+};
 
 struct SimHost {
     int n[3] = {0, 0, 0};
@@ -740,6 +753,7 @@ static void layout_workspace(vl_ctx *ctx)
 
 int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_bytes)
 {
+    const MarkerRange range_("vl_finalize");
     if (int rc = check_ctx(ctx)) return rc;
     if (ctx->finalized) return fail(VL_E_STATE, "context already finalized");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(VL_E_ARG, "dt must be finite and > 0");
@@ -1038,6 +1052,7 @@ int vl_finalize(vl_ctx *ctx, double dt, size_t *field_elems, size_t *workspace_b
 
 int vl_resize_cells(vl_ctx *ctx, int sim, int max_cells, size_t *workspace_bytes)
 {
+    const MarkerRange range_("vl_resize_cells");
     if (int rc = check_sim(ctx, sim)) return rc;
     if (!ctx->finalized) return fail(VL_E_STATE, "before vl_finalize, vl_reserve_cells sets the capacity");
     if (max_cells < 0 || max_cells > (1 << 24)) return fail(VL_E_ARG, "max_cells must be in [0, 2^24]");
@@ -1057,6 +1072,7 @@ int vl_resize_cells(vl_ctx *ctx, int sim, int max_cells, size_t *workspace_bytes
 
 int vl_bind(vl_ctx *ctx, void *field_dev, void *workspace_dev, void *stream)
 {
+    const MarkerRange range_("vl_bind");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->finalized) return fail(VL_E_STATE, "call vl_finalize before vl_bind");
     if (!field_dev || !workspace_dev) return fail(VL_E_ARG, "field and workspace must not be null");
@@ -1211,6 +1227,7 @@ int vl_get_field(vl_ctx *ctx, int sim, void *dst, int dst_is_device, int layout)
 
 int vl_snapshot(vl_ctx *ctx, int sim, void *stage_dev, void *host_dst)
 {
+    const MarkerRange range_("vl_snapshot");
     if (int rc = check_sim(ctx, sim)) return rc;
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (!stage_dev || !host_dst) return fail(VL_E_ARG, "stage_dev and host_dst must not be null");
@@ -1235,6 +1252,7 @@ int vl_snapshot(vl_ctx *ctx, int sim, void *stage_dev, void *host_dst)
 
 int vl_snapshot_wait(vl_ctx *ctx)
 {
+    const MarkerRange range_("vl_snapshot_wait");
     if (int rc = check_ctx(ctx)) return rc;
     if (ctx->copy_stream) VL_HIP(hipStreamSynchronize(ctx->copy_stream));
     ctx->snap_pending = false;
@@ -1376,17 +1394,20 @@ static int upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const do
 int vl_upload_cells(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
                     const double *U, const double *rho_star, int *n_out_of_domain)
 {
+    const MarkerRange range_("vl_upload_cells");
     return upload_cells(ctx, sim, n, pos, V, S, U, rho_star, n_out_of_domain, false);
 }
 
 int vl_upload_cells_dev(vl_ctx *ctx, int sim, int n, const double *pos, const double *V, const double *S,
                         const double *U, const double *rho_star, int *n_out_of_domain)
 {
+    const MarkerRange range_("vl_upload_cells_dev");
     return upload_cells(ctx, sim, n, pos, V, S, U, rho_star, n_out_of_domain, true);
 }
 
 int vl_step(vl_ctx *ctx, int n_steps)
 {
+    const MarkerRange range_("vl_step");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (n_steps < 0) return fail(VL_E_ARG, "n_steps must be >= 0");
@@ -1440,6 +1461,7 @@ int vl_step(vl_ctx *ctx, int n_steps)
 
 int vl_sync(vl_ctx *ctx)
 {
+    const MarkerRange range_("vl_sync");
     if (int rc = check_ctx(ctx)) return rc;
     VL_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->bound) {
@@ -1603,6 +1625,7 @@ static std::string tune_key(const vl_ctx *ctx)
 
 int vl_tune(vl_ctx *ctx, const char *cache_path)
 {
+    const MarkerRange range_("vl_tune");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (ctx->precision != VL_F32) return VL_OK;  // the plain path has one shape
@@ -1886,6 +1909,7 @@ static int replay_step(vl_ctx *ctx, char *aws, const AdjLayout &A)
 int vl_adjoint(vl_ctx *ctx, int n_steps, int ckpt_every, void *adj_workspace, const void *grad_final_dev,
                void *grad_rho0_dev, double *dD, double *dlambda, double *dS_dev, double *dU_dev)
 {
+    const MarkerRange range_("vl_adjoint");
     if (int rc = check_ctx(ctx)) return rc;
     if (!ctx->bound) return fail(VL_E_STATE, "call vl_bind first");
     if (ctx->precision != VL_F32) return fail(VL_E_STATE, "the adjoint runs on the FP32 path");

@@ -195,3 +195,36 @@ def test_mass_noalloc_rejects_bad_arguments_on_the_host():
     assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F32, 10, 2, 9, 4096) == vb.VL_E_ARG  # overlapping volumes
     assert _code(vb.vl_mass_noalloc, 4098, vb.VL_F32, 10, 1, 10, 4096) == vb.VL_E_ARG  # misaligned field
     assert _code(vb.vl_mass_noalloc, 4096, vb.VL_F64, 10, 1, 10, 4100) == vb.VL_E_ARG  # misaligned output
+
+
+def _roctx():
+    """The roctx library that libvoxlod.so loaded (its path from this process's maps)."""
+    C.CDLL(vb.LIB_PATH)
+    paths = {ln.split()[-1] for ln in open("/proc/self/maps") if "librocprofiler-sdk-roctx" in ln}
+    assert len(paths) == 1, paths
+    r = C.CDLL(paths.pop())
+    r.roctxRangePushA.restype, r.roctxRangePushA.argtypes = C.c_int, [C.c_char_p]
+    r.roctxRangePop.restype = C.c_int
+    return r
+
+
+def test_calls_close_the_roctx_ranges_they_open():
+    # every entry point that opens a range (rocprofv3 --marker-trace) closes it
+    # on each return path, including the early error returns
+    r = _roctx()
+    assert r.roctxRangePushA(b"probe") == 0 and r.roctxRangePop() == 0
+    h = vb.vl_create(1, vb.VL_F32)
+    try:
+        assert _code(vb.vl_finalize, h, 0.01) == vb.VL_E_STATE  # no grid: returns inside its range
+        assert _code(vb.vl_step, h, 1) == vb.VL_E_STATE  # not bound
+        assert _code(vb.vl_tune, h, None) == vb.VL_E_STATE
+        assert _code(vb.vl_resize_cells, h, 0, 10) == vb.VL_E_STATE
+        vb.vl_set_grid(h, 0, 9, 8, 7, 10, 10, 10, 0, 0, 0)
+        vb.vl_set_substrates(h, 0, [1e3], [0.1])
+        vb.vl_finalize(h, 0.01)
+        assert _code(vb.vl_step, h, 1) == vb.VL_E_STATE  # finalized, not bound
+    finally:
+        vb.vl_destroy(h)
+    # nothing is left open on this thread: a new range starts at level 0
+    assert r.roctxRangePushA(b"probe") == 0
+    assert r.roctxRangePop() == 0
