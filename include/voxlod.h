@@ -315,8 +315,10 @@ int vl_check_finite(vl_ctx *ctx, long long *bad);
  * barrier.  VL_OPT_PERSISTENT_GRID: workgroups of that launch (0 = as many
  * as fit on the device at once).  VL_OPT_WAIT_LIMIT_US: microseconds a tile
  * may wait for the previous sweep of its volume before it gives up (default
- * 2000000); giving up makes the next vl_sync fail with VL_E_STATE, so a step
- * can never hang (the limit exists for tests of that path). */
+ * 2000000); once one wait has given up, every later wait of the same launch
+ * gives up at once, so the limit bounds the launch.  Giving up makes the next
+ * vl_sync fail with VL_E_STATE, so a step can never hang (the limit exists
+ * for tests of that path). */
 #define VL_OPT_STEP_MODE 2
 #define VL_OPT_PERSISTENT_GRID 3
 #define VL_OPT_WAIT_LIMIT_US 4

@@ -161,7 +161,7 @@ struct vl_ctx {
     int queue_phase[4] = {0, 0, 0, 0};
     size_t q_ids_off = 0, q_prefix_off = 0;  // offsets into itable
     size_t o_qcounters = 0, o_qerror = 0;
-    int wait_limit_us = 2000000;  // a tile of the one-launch step waits at most this long
+    int wait_limit_us = 2000000;  // a wait of the one-launch step past this gives up, and so do the launch's later waits
 
     // workspace layout (byte offsets)
     size_t o_subs = 0, o_coef32 = 0, o_coefh = 0, o_coef64 = 0, o_itable = 0, o_lltable = 0, o_faces = 0,

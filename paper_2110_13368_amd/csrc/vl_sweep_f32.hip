@@ -521,9 +521,11 @@ sweep_f32(SweepLaunch L, const SubDev *__restrict__ subs, const double2 *__restr
 // volume).  A y (z) tile of a volume first waits until all x (y) tiles of
 // that volume are done.  Those tiles were taken earlier by workgroups that
 // are running and never wait on later tiles, so the waits always end,
-// whatever the grid size.  A wait that exceeds spin_limit sets *error and
-// gives up (the step is then wrong, but every wave exits).  The last
-// workgroup to leave resets the counters for the next launch.
+// whatever the grid size.  A wait that exceeds Q.wait_ticks sets *error and
+// gives up (the step is then wrong, but every wave exits); every later wait
+// of the launch sees the error and gives up at once, so the limit bounds the
+// launch, not each of its tiles.  The last workgroup to leave resets the
+// counters for the next launch.
 template <int CAP>
 __global__ void __launch_bounds__(128)
 sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const double2 *__restrict__ coef,
@@ -556,11 +558,18 @@ sweep_step_persistent(StepQueue Q, const SubDev *__restrict__ subs, const double
                 // stale line of it; RMW atomics act at the coherence point.
                 // Q.zero (0, but not a constant here) keeps the compiler from
                 // turning the idempotent add into a load.
-                if (__hip_atomic_fetch_add(d, Q.zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                // A launch in which a wait has already given up waits no more.
+                auto gave_up = [&]() {
+                    return __hip_atomic_fetch_add(Q.error, (int)Q.zero, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) != 0;
+                };
+                if (__hip_atomic_fetch_add(d, Q.zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need &&
+                    !gave_up()) {
                     const unsigned long long t0 = wall_clock64();
+                    unsigned polls = 0;
                     while (__hip_atomic_fetch_add(d, Q.zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         __builtin_amdgcn_s_sleep(2);
-                        if (wall_clock64() - t0 > Q.wait_ticks) {
+                        if (wall_clock64() - t0 > Q.wait_ticks || ((++polls & 63u) == 0 && gave_up())) {
                             atomicOr(Q.error, 1);
                             break;
                         }
