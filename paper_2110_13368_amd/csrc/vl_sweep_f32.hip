@@ -57,6 +57,14 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     constexpr int kW = XStage<CAP>::W;    // stage columns per chunk
     constexpr int kSX = XStage<CAP>::SX;  // stage row stride
     constexpr int kChunks = (CAP + kW - 1) / kW;
+    // x with 32-column chunks (lines of up to 65 voxels): each LDS-DMA load
+    // and each store instruction moves two rows of the tile (lanes 0-31 row
+    // 2p, lanes 32-63 row 2p+1), where one row per instruction would leave
+    // half the lanes idle.  Row q sits at (q/2)*kPS + (q%2)*32 in the stage,
+    // and lane l solves row xrow(l) = 2(l mod 32) + l/32, so that the 32
+    // lanes of each half read their own rows without bank conflicts.
+    constexpr bool kPair = AXIS == 0 && kW == 32;
+    constexpr int kPS = 2 * kW + 1;
     // NT (z launches of long lines whose tiles re-read no voxel after their
     // stores): the rows lie a plane apart and each 256-byte row is read and
     // written once, so the loads and stores are non-temporal (5 % faster on
@@ -71,6 +79,9 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const bool top = (wave == 0);
+    const int xrow = kPair ? 2 * (lane & 31) + (lane >> 5) : lane;  // this lane's row of an x tile
+    const int xcol = kPair ? (lane & 31) : lane;                    // the chunk column a lane moves
+    auto srow = [&](int q) { return kPair ? (q >> 1) * kPS + (q & 1) * 32 : q * kSX; };
 
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
     const int n = S.n[AXIS];
@@ -100,8 +111,8 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
     if (AXIS == 0) {
         const int nrows = ny * nz;
         const int r0 = local * kTileLines;
-        const int r = min(r0 + lane, nrows - 1);
-        line_ok = r0 + lane < nrows;
+        const int r = min(r0 + xrow, nrows - 1);
+        line_ok = r0 + xrow < nrows;
         const int j = r % ny, k = r / ny;
         on = (j == 0 ? 1 << 2 : 0) | (j == ny - 1 ? 1 << 3 : 0) |
              (k == 0 ? 1 << 4 : 0) | (k == nz - 1 ? 1 << 5 : 0);
@@ -189,13 +200,19 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
         for (int c = 0; c < kChunks; ++c) {
             if (c * kW < nel) {
                 const int cs = top ? c * kW : n - kW * (c + 1);
-                const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
+                const int col = top ? min(cs + xcol, nel - 1) : max(cs + xcol, n - cb);
                 const unsigned cb4 = (unsigned)col * 4u;
                 // DMA straight into LDS: lane j's value of row q lands in
-                // st[q*kSX + j]; no VGPR staging, all 64 rows in flight.  With
-                // 32-column chunks only lanes 0-31 take part (the DMA writes
-                // lane j at the row's start + j).
-                if (kW == 64 || lane < kW) {
+                // st[q*kSX + j]; no VGPR staging, all 64 rows in flight.  The
+                // DMA writes lane j at the instruction's base + j, so with
+                // 32-column chunks lanes 32-63 land on the pair's second row.
+                if (kPair) {
+#pragma unroll
+                    for (int p = 0; p < 32; ++p)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            rs, (__attribute__((address_space(3))) void *)(st + p * kPS), 4,
+                            (int)(cb4 + (unsigned)(min(2 * p + (lane >> 5), xrows_left - 1) * row_b)), 0, 0, 0);
+                } else {
 #pragma unroll
                     for (int q = 0; q < 64; ++q)
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(
@@ -204,15 +221,15 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
                 }
                 __builtin_amdgcn_s_waitcnt(0);
                 wave_sync_lds();
-                carry_chunk(cs, kW, [&](int q, int cc) { return st + q * kSX + cc; });
+                carry_chunk(cs, kW, [&](int q, int cc) { return st + srow(q) + cc; });
                 if (top) {
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
-                        if (c * kW + jj < CAP && c * kW + jj < nel) v[c * kW + jj] = st[lane * kSX + jj];
+                        if (c * kW + jj < CAP && c * kW + jj < nel) v[c * kW + jj] = st[srow(xrow) + jj];
                 } else {
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
-                        if (c * kW + jj < CAP && c * kW + jj < nel) v[c * kW + jj] = st[lane * kSX + kW - 1 - jj];
+                        if (c * kW + jj < CAP && c * kW + jj < nel) v[c * kW + jj] = st[srow(xrow) + kW - 1 - jj];
                 }
                 wave_sync_lds();
             }
@@ -262,7 +279,7 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
         if (AXIS == 0) {
             rm = bload(rs, lane_b + (unsigned)m * 4u, 0);
             if (carried && line_ok) {  // the middle column's source, if any, from this lane's own x-line
-                const int r = c_r0 + lane;
+                const int r = c_r0 + xrow;
                 const int want = r * nx + m;
                 for (int e = c_xs[r]; e < c_xs[r + 1]; ++e) {
                     const int vox = c_vox[e];
@@ -312,22 +329,28 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
                     if (top) {
 #pragma unroll
                         for (int jj = 0; jj < kW; ++jj)
-                            if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + jj] = v[c * kW + jj];
+                            if (c * kW + jj < CAP && c * kW + jj < nel) st[srow(xrow) + jj] = v[c * kW + jj];
                     } else {
 #pragma unroll
                         for (int jj = 0; jj < kW; ++jj)
-                            if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + kW - 1 - jj] = v[c * kW + jj];
+                            if (c * kW + jj < CAP && c * kW + jj < nel) st[srow(xrow) + kW - 1 - jj] = v[c * kW + jj];
                     }
                     wave_sync_lds();
                     const int cs = top ? c * kW : n - kW * (c + 1);
-                    const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
+                    const int col = top ? min(cs + xcol, nel - 1) : max(cs + xcol, n - cb);
                     const int so = col - cs;
                     const unsigned cb4 = (unsigned)col * 4u;
-                    // with 32-column chunks lanes 32-63 have no column of
-                    // their own (the bottom wave's would lie past the line)
+                    if (kPair) {
 #pragma unroll 16
-                    for (int q = 0; q < 64; ++q)
-                        if (q < xrows_left && (kW == 64 || lane < kW)) bstore(rr, cb4, q * row_b, st[q * kSX + so]);
+                        for (int p = 0; p < 32; ++p) {
+                            const int q = 2 * p + (lane >> 5);
+                            if (q < xrows_left) bstore(rr, cb4 + (unsigned)(q * row_b), 0, st[srow(q) + so]);
+                        }
+                    } else {
+#pragma unroll 16
+                        for (int q = 0; q < 64; ++q)
+                            if (q < xrows_left) bstore(rr, cb4, q * row_b, st[q * kSX + so]);
+                    }
                     wave_sync_lds();
                 }
             }
@@ -417,20 +440,28 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
                 if (top) {
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
-                        if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + jj] = v[c * kW + jj];
+                        if (c * kW + jj < CAP && c * kW + jj < nel) st[srow(xrow) + jj] = v[c * kW + jj];
                 } else {
 #pragma unroll
                     for (int jj = 0; jj < kW; ++jj)
-                        if (c * kW + jj < CAP && c * kW + jj < nel) st[lane * kSX + kW - 1 - jj] = v[c * kW + jj];
+                        if (c * kW + jj < CAP && c * kW + jj < nel) st[srow(xrow) + kW - 1 - jj] = v[c * kW + jj];
                 }
                 wave_sync_lds();
                 const int cs = top ? c * kW : n - kW * (c + 1);
-                const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
+                const int col = top ? min(cs + xcol, nel - 1) : max(cs + xcol, n - cb);
                 const int so = col - cs;
                 const unsigned cb4 = (unsigned)col * 4u;
+                if (kPair) {
 #pragma unroll 16
-                for (int q = 0; q < 64; ++q)
-                    if (q < xrows_left && (kW == 64 || lane < kW)) bstore(rs, cb4, q * row_b, st[q * kSX + so]);
+                    for (int p = 0; p < 32; ++p) {
+                        const int q = 2 * p + (lane >> 5);
+                        if (q < xrows_left) bstore(rs, cb4 + (unsigned)(q * row_b), 0, st[srow(q) + so]);
+                    }
+                } else {
+#pragma unroll 16
+                    for (int q = 0; q < 64; ++q)
+                        if (q < xrows_left) bstore(rs, cb4, q * row_b, st[q * kSX + so]);
+                }
                 wave_sync_lds();
             }
         }
