@@ -120,6 +120,10 @@ __device__ __forceinline__ void adjoint_tile(const SubDev &S, int local, int til
                 const int cs = top ? c * 64 : n - 64 * (c + 1);
                 const int col = top ? min(cs + lane, nel - 1) : max(cs + lane, n - cb);
                 const unsigned cb4 = (unsigned)col * 4u;
+                // the previous chunk's stage reads complete before the DMA
+                // reuses the stage (LDS-DMA writes are not ordered after
+                // earlier LDS reads)
+                if (c > 0) __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
                 for (int q = 0; q < 64; ++q)
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(

@@ -198,6 +198,9 @@ __device__ __forceinline__ void x_load_wide(float (&v)[CAP], __amdgpu_buffer_rsr
         if (c * 64 < nel) {
             const int cbase = top ? c * 64 : n - 64 * (c + 1);
             const int col = top ? min(cbase + 4 * gq, n - 4) : cbase + 4 * gq;
+            // the previous chunk's stage reads complete before the DMA reuses
+            // the stage (LDS-DMA writes are not ordered after earlier LDS reads)
+            if (c > 0) __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
             for (int k = 0; k < 16; ++k)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(

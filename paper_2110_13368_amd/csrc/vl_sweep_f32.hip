@@ -202,6 +202,11 @@ __device__ __forceinline__ void sweep_tile(const SubDev &S, int local, const dou
                 const int cs = top ? c * kW : n - kW * (c + 1);
                 const int col = top ? min(cs + xcol, nel - 1) : max(cs + xcol, n - cb);
                 const unsigned cb4 = (unsigned)col * 4u;
+                // the previous chunk's reads of the stage must be complete
+                // before this chunk's DMA overwrites it: LDS-DMA writes are
+                // ordered after the wave's earlier LDS reads neither by the
+                // compiler nor by the hardware
+                if (c > 0) __builtin_amdgcn_s_waitcnt(0);
                 // DMA straight into LDS: lane j's value of row q lands in
                 // st[q*kSX + j]; no VGPR staging, all 64 rows in flight.  The
                 // DMA writes lane j at the instruction's base + j, so with
